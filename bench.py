@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the PSR-NQS hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic samples:
+  pack spins -> connected configurations (Heisenberg, Marshall basis) ->
+  log psi of the samples and of every connected configuration (streamed in
+  chunks) -> E_loc and its FP64 mean / variance -> VMC weights ->
+  per-sample gradients O_s (reverse-scan adjoint with checkpoints) -> FP64
+  gradient estimate g = (2/B) sum (E_loc - mean) O_s.
+
+Metric: site-evals/s of log psi forward + backward, i.e.
+  N * (samples + connected configurations)  [forward]
++ N * samples                               [backward]
+per second of wall time of the timed steps (inputs resident in HBM).
+
+Default workload: 32x32 open Heisenberg lattice, 3-layer 2D minGRU, d = 128,
+4096 Neel-like zero-magnetisation samples (~1.9k connected each), BF16
+projections.  The FP32 path is measured on the same model with a smaller batch
+(the rate is per site-eval) and reported beside it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: lattice side, layers, d, samples, FP32-comparison samples, seed index
+    "heisenberg32x32": dict(L=32, nl=3, d=128, B=4096, B_fp32=256, k=3),
+    "heisenberg52x52": dict(L=52, nl=4, d=256, B=256, B_fp32=32, k=4),
+    "heisenberg20x20": dict(L=20, nl=3, d=128, B=8192, B_fp32=512, k=2),
+    "heisenberg10x10": dict(L=10, nl=2, d=64, B=4096, B_fp32=1024, k=1),
+}
+
+PEAK = {  # MI355X datasheet peaks (dense)
+    "bf16_tflops": 2500.0,
+    "fp32_tflops": 157.3,
+    "hbm_gbs": 8000.0,
+}
+
+
+def flops_per_site(nl: int, d: int) -> float:
+    """Algorithmic MFMA flops of one site-eval forward: 2 * (2 d^2 + 5 d^2 (nl-1) + 2 d)."""
+    return 2.0 * (2 * d * d + 5 * d * d * (nl - 1) + 2 * d)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heisenberg32x32", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=0, help="override the number of samples")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--chunk", type=int, default=32768)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: the hot path has no cross-GPU step "
+                                   "(samples shard with zero communication; see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2605_13807_amd as P
+    import psr_inputs as I
+
+    W = WORKLOADS[args.workload]
+    L, nl, d, k = W["L"], W["nl"], W["d"], W["k"]
+    B = args.batch or W["B"]
+    N = L * L
+    dev = torch.device("cuda:0")
+    prec = P.BF16 if args.precision == "bf16" else P.FP32
+
+    def setup(prec_, B_):
+        m = P.Model(P.SNAKE_2D, L, L, nl, d, prec_)
+        th = torch.from_numpy(I.params(P.param_count(m), d, 1000 + k)).to(dev)
+        s_np = I.spins_neel_like(B_, L, L, 2000 + k)
+        s = torch.from_numpy(s_np).to(dev)
+        H = P.Hamiltonian(P.HEISENBERG, L, L)
+        conn = P.connected(H, s)
+        M = int(conn["n_conn"].sum().item())
+        del conn
+        ws_e = P._workspace(m, P.OP_LOCAL_ENERGY, B_, dev, args.chunk)
+        ws_b = P._workspace(m, P.OP_BACKWARD, B_, dev)
+        return m, th, s, s_np, H, M, ws_e, ws_b
+
+    def step(m, th, s, H, ws_e, ws_b):
+        e, st, lp = P.local_energy(m, th, H, s, chunk_seqs=args.chunk, ws=ws_e)
+        w = P.vmc_weights(e, st)
+        O, lpb, g = P.logpsi_backward(m, th, s, w=w, want_O=True, ws=ws_b)
+        return e, st, O, g
+
+    def timed(prec_, B_, steps, warmup):
+        m, th, s, s_np, H, M, ws_e, ws_b = setup(prec_, B_)
+        for _ in range(warmup):
+            step(m, th, s, H, ws_e, ws_b)
+        torch.cuda.synchronize()
+        P.timing_begin()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = step(m, th, s, H, ws_e, ws_b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fwd_ms, fwd_launches = P.timing_end()
+        site_evals = N * (B_ + M) + N * B_
+        return dict(m=m, th=th, s=s, s_np=s_np, H=H, M=M, dt=(t1 - t0), steps=steps, fwd_ms=fwd_ms,
+                    fwd_launches=fwd_launches, site_evals=site_evals, out=out, B=B_)
+
+    print(f"# workload {args.workload}: {L}x{L}, {nl} layers, d={d}, B={B}, {args.precision}", file=sys.stderr,
+          flush=True)
+    r = timed(prec, B, args.steps, args.warmup)
+    ms_step = 1000.0 * r["dt"] / r["steps"]
+    value = r["site_evals"] * r["steps"] / r["dt"]
+    print(f"# main: {ms_step:.1f} ms/step, {value:.4e} site-evals/s, connected {r['M']}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (the fused forward), from the live HIP-event timing
+    F = flops_per_site(nl, d)
+    fwd_flops = F * N * (B + r["M"]) * r["steps"]       # forward site-evals of the timed steps
+    fwd_s = r["fwd_ms"] / 1000.0
+    achieved = fwd_flops / fwd_s / 1e12
+    peak = PEAK["bf16_tflops"] if prec == P.BF16 else PEAK["fp32_tflops"]
+    roofline = {
+        "bound": "mfma",
+        "kernel": "fwd_kernel",
+        "achieved": round(achieved, 2),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "launches": r["fwd_launches"],
+        "avg_launch_ms": round(r["fwd_ms"] / max(1, r["fwd_launches"]), 4),
+        "flops_per_site_eval": F,
+        "fwd_share_of_step": round(fwd_s / r["dt"], 4),
+    }
+
+    # FP32 path on the same model (smaller batch; rate per site-eval)
+    fp32 = None
+    if not args.no_fp32 and prec == P.BF16:
+        B32 = min(B, W["B_fp32"])
+        r32 = timed(P.FP32, B32, 1, 1)
+        v32 = r32["site_evals"] / r32["dt"]
+        fp32 = {"value": v32, "samples": B32, "ms_per_step": round(1000.0 * r32["dt"], 2),
+                "speedup_bf16_over_fp32": round(value / v32, 3),
+                "fwd_tflops": round(F * N * (B32 + r32["M"]) / (r32["fwd_ms"] / 1000.0) / 1e12, 2)}
+        print(f"# fp32: {v32:.4e} site-evals/s", file=sys.stderr, flush=True)
+        del r32
+
+    # CPU oracle baseline on a bounded sample, and the E_loc error on that sample
+    cpu = None
+    err = None
+    if not args.no_cpu:
+        from oracle import grad as OG
+        from oracle import hamiltonian as OH
+        from oracle import model as OM
+        om = OM.Model("snake2d", L, L, nl, d)
+        th_np = r["th"].cpu().numpy()
+        oh = OH.Hamiltonian("heisenberg", L, L)
+        n_s = 1
+        sub = r["s_np"][:n_s]
+        threads = torch.get_num_threads()
+        t0 = time.perf_counter()
+        e_ref = OH.local_energy(lambda c: OM.logpsi(th_np, c, om), oh, sub)
+        t_fwd = time.perf_counter() - t0
+        conn = OH.connected(oh, sub)
+        m_sub = int(conn["n_conn"].sum())
+        t1 = time.perf_counter()
+        OG.per_sample_grad(th_np, sub, om)
+        t_bwd = time.perf_counter() - t1
+        cpu_site_evals = N * (n_s + m_sub) + N * n_s
+        cpu = {"value": cpu_site_evals / (t_fwd + t_bwd), "unit": "site-evals/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{n_s} sample(s) of the workload with all {m_sub} connected configurations "
+                         f"(float64 numpy forward) + 1 per-sample gradient (float64 torch autograd); "
+                         f"{t_fwd + t_bwd:.1f} s"}
+        e_gpu = r["out"][0][:n_s].cpu().numpy()
+        err = {"eloc_rel_err_vs_fp64_oracle": float(np.max(np.abs(e_gpu - e_ref) / np.maximum(np.abs(e_ref), 1.0))),
+               "samples_checked": n_s}
+        print(f"# cpu oracle: {cpu['value']:.4e} site-evals/s ({t_fwd + t_bwd:.1f} s)", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "site-evals/s for log psi fwd+bwd (bf16 vs fp32, same GPU) at stated E_loc error",
+        "value": value,
+        "unit": "site-evals/s",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if prec == P.BF16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: open Heisenberg {L}x{L}, 2D minGRU {nl} layers d={d}, "
+                               f"{B} Neel-like samples, all bond-exchange connected configurations "
+                               f"({r['M']} total), E_loc + per-sample gradients",
+                   "samples": B, "connected": r["M"], "sites": N, "chunk_seqs": args.chunk,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp32_path": fp32,
+        "error": err,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

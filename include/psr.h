@@ -1,0 +1,196 @@
+/*
+ * psr.h -- C ABI of libpsr, the MI355X (gfx950) hot path of the parallel-scan
+ * recurrent neural quantum state (PSR-NQS): batched log psi of an
+ * autoregressive 1D/2D minGRU wave function, the configurations a Hamiltonian
+ * connects to each sample, the local energy E_loc and the per-sample
+ * gradient d log psi / d theta.
+ *
+ * Paper: E. Merali, M. Hibat-Allah, M. Kohandel, R. T. Scalettar, E. Khatami,
+ * "Parallel Scan Recurrent Neural Quantum States for Scalable Variational
+ * Monte Carlo".  Section references below are to that paper.
+ *
+ * General rules
+ *  - Every pointer argument named as device memory must point to HIP device
+ *    memory of the current device; the caller owns it and keeps it alive until
+ *    the work queued on `stream` has finished.  Pointers to descriptor structs
+ *    are host pointers, read before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Compute calls only queue work on it and return; they never synchronise,
+ *    except where a call says otherwise.
+ *  - Return value: PSR_OK (0) or a negative PSR_E* code.  Arguments are checked
+ *    on the host before anything is queued, so an error return queues no work
+ *    and writes no output.  psr_last_error() gives a message for the last
+ *    failing call of the calling thread.
+ *  - Spins are int8 in {0, 1}, 1 = spin up (sigma^z = +1), stored per sample
+ *    in lattice row-major order: site a = y * lx + x.  Values outside {0, 1}
+ *    are a precondition violation (use psr_check_spins to test a batch).
+ *  - Parameters theta are float32, one flat vector in the layout given by
+ *    psr_param_offsets (also the layout of every gradient row).
+ */
+#ifndef PSR_H
+#define PSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PSR_OK            0
+#define PSR_EINVAL       -1   /* invalid argument */
+#define PSR_EUNSUPPORTED -2   /* valid request that this build does not support */
+#define PSR_ENOMEM       -3   /* workspace too small or allocation failed */
+#define PSR_EDEVICE      -4   /* HIP runtime error */
+#define PSR_ECAPACITY    -5   /* max_conn smaller than a sample's connected count */
+#define PSR_EDATA        -6   /* spins outside {0, 1} (psr_check_spins) */
+
+/* ---- model ------------------------------------------------------------- */
+#define PSR_CHAIN_1D   0  /* Sec. II.C, Eq. (minGRU): one layer on a chain, head on h_t */
+#define PSR_SNAKE_2D   1  /* Sec. II.F-G: stacked 2D minGRU along the zigzag path */
+
+#define PSR_FP32       0  /* projections on FP32 MFMA */
+#define PSR_BF16       1  /* projections on BF16 MFMA, FP32 accumulation */
+
+typedef struct {
+    int32_t geometry;   /* PSR_CHAIN_1D or PSR_SNAKE_2D */
+    int32_t lx, ly;     /* lattice sides; the chain has ly = 1 and lx = N */
+    int32_t n_layers;   /* chain: 1 */
+    int32_t d;          /* hidden size d = d_h; 32, 64, 128 or 256 */
+    int32_t precision;  /* PSR_FP32 or PSR_BF16 (input type of the dense projections) */
+    int32_t ckpt_rows;  /* rows per backward checkpoint chunk; 0 = max(1, 64 / lx) */
+} psr_model_desc;
+
+/*
+ * Parameter layout (Sec. II.C for the chain, Sec. II.F-G for the snake):
+ *   chain : W_z[d][2], b_z[d], W_h[d][2], b_h[d], W_o[2][d], b_o[2]
+ *   snake : for each layer l = 0..n_layers-1
+ *             W_z[d][du], b_z[d], W_h[d][du+d], b_h[d], C[d][d], D[d][du]
+ *           with du = 4 at l = 0 (one-hot spins of the two causal
+ *           predecessors) and du = d above; then W_o[2][d], b_o[2].
+ * Matrices are row-major (output index first).  W_h multiplies [u, h_V].
+ */
+int64_t psr_param_count(const psr_model_desc* m);  /* P, or a negative code */
+
+/* offsets[k] = first entry of tensor k (k = 0..n-1) and offsets[n] = P.
+ * `offsets` must hold at least 6 * n_layers + 3 entries; *n_tensors gets n. */
+int psr_param_offsets(const psr_model_desc* m, int64_t* offsets, int32_t* n_tensors);
+
+/* ---- Hamiltonian ------------------------------------------------------- */
+#define PSR_TFIM        0  /* H = -J sum_<ab> Z_a Z_b - h sum_a X_a (Sec. III.B, open chain) */
+#define PSR_HEISENBERG  1  /* H = J sum_<ab> S_a . S_b, S = sigma/2 (Sec. III.C, open square lattice) */
+
+typedef struct {
+    int32_t kind;       /* PSR_TFIM or PSR_HEISENBERG */
+    int32_t lx, ly;     /* must equal the model's lattice; bonds are the open-boundary nearest neighbours */
+    int32_t marshall;   /* Heisenberg only: 1 = Marshall-rotated basis (off-diagonal -J/2, Sec. III.C) */
+    int32_t pbc;        /* must be 0: open boundaries, as in the paper */
+    double  J, h;
+} psr_hamiltonian;
+
+/* Largest connected count of one sample: N for TFIM, the bond count 2 lx ly - lx - ly for Heisenberg. */
+int64_t psr_max_connected(const psr_hamiltonian* H);
+
+/* ---- workspace --------------------------------------------------------- */
+#define PSR_OP_LOGPSI        0
+#define PSR_OP_LOCAL_ENERGY  1
+#define PSR_OP_BACKWARD      2
+
+/* Device workspace bytes that `op` needs for a batch of `batch` samples
+ * (`chunk_seqs` only matters for PSR_OP_LOCAL_ENERGY).  Negative on error. */
+int64_t psr_workspace_bytes(const psr_model_desc* m, int32_t op, int64_t batch, int64_t chunk_seqs);
+
+/* ---- compute calls ------------------------------------------------------ */
+
+/*
+ * log psi of a batch (Sec. III.B: psi is the square root of the
+ * autoregressive probability, log psi = 1/2 sum_t log p(sigma_t | sigma_<t)),
+ * evaluated row by row with a parallel scan along each zigzag row (Sec. II.F).
+ *   theta      device, float[P]
+ *   spins      device, int8[B][N]
+ *   logpsi     device, float[B]                     (out)
+ *   logp_site  device, float[B][N] or NULL          (out) log p of each site, row-major
+ *   ws         device workspace of psr_workspace_bytes(m, PSR_OP_LOGPSI, B, 0) bytes
+ */
+int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B,
+               float* logpsi, float* logp_site, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Connected configurations of each sample (Sec. II.A: the extra forward passes
+ * of the local energy), in canonical order: sites ascending; at each site a the
+ * bond (a, a+1) before the bond (a, a+lx).  Heisenberg: one entry per bond
+ * whose spins differ (the exchange), element -J/2 (Marshall) or +J/2.  TFIM:
+ * one entry per site (single flip), element -h.
+ *   spins   device int8[B][N]
+ *   conn    device int8[B][max_conn][N] or NULL   (out) the configurations
+ *   desc    device uint32[B][max_conn][2] or NULL (out) {sample, a | b << 16};
+ *           sites a and b are flipped (a == b: one flip)
+ *   mel     device float[B][max_conn] or NULL     (out) <sigma|H|sigma'>
+ *   n_conn  device int32[B]                       (out)
+ *   diag    device float[B] or NULL               (out) <sigma|H|sigma>
+ * Entries k >= n_conn[s] of a sample are left untouched.  max_conn must be at
+ * least psr_max_connected(H) (else PSR_ECAPACITY); N must be <= 65535.
+ */
+int psr_connected(const psr_hamiltonian* H, const int8_t* spins, int64_t B, int64_t max_conn,
+                  int8_t* conn, uint32_t* desc, float* mel, int32_t* n_conn, float* diag,
+                  void* stream);
+
+/*
+ * Local energies E_loc(s) = diag(s) + sum_k mel_k psi(sigma'_k) / psi(sigma_s)
+ * and their batch mean and variance (1/B normaliser) accumulated in FP64.
+ * The connected configurations are evaluated in chunks of `chunk_seqs`
+ * sequences (0 = 32768), so device memory stays O(chunk), not O(B * N).
+ *   eloc    device double[B]      (out)
+ *   stats   device double[2]      (out) mean, variance
+ *   logpsi  device float[B] or NULL (out) log psi of the samples
+ */
+int psr_local_energy(const psr_model_desc* m, const float* theta, const psr_hamiltonian* H,
+                     const int8_t* spins, int64_t B, int64_t chunk_seqs,
+                     double* eloc, double* stats, float* logpsi,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Per-sample gradients O_s = d log psi(sigma_s) / d theta by a reverse-mode
+ * adjoint of the row recurrence (reverse scan along each zigzag row).  The
+ * forward keeps only the row frontier at checkpoint-chunk boundaries and each
+ * chunk is recomputed before its reverse sweep.
+ *   O       device float[B][P] or NULL   (out) one gradient row per sample
+ *   logpsi  device float[B] or NULL      (out)
+ *   w, g    device double[B], double[P]  both NULL or both set: g = sum_s w_s O_s (FP64)
+ * At least one of O and g must be set.
+ */
+int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B,
+                        float* O, float* logpsi, const double* w, double* g,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * VMC weights of the energy-gradient estimator (Sec. III.B, stochastic energy
+ * gradient with real psi): w_s = (2 / B) (E_loc(s) - mean), mean = stats[0].
+ * With these weights psr_logpsi_backward's g is the gradient estimate
+ * (2/B) sum_s (E_loc(s) - mean) O_s.   eloc, stats, w: device doubles.
+ */
+int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, void* stream);
+
+/* Synchronous check of a spin batch: PSR_OK if every value is 0 or 1, PSR_EDATA otherwise. */
+int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Timing of the forward (log psi) kernel, for measurement tools.  After
+ * psr_timing_begin(), every forward-kernel launch that this thread queues is
+ * bracketed by two HIP events recorded on the launch's stream.
+ * psr_timing_end() waits for those events, returns the summed kernel time in
+ * milliseconds and the number of launches, and stops recording.  Two event
+ * records per launch are the only overhead. */
+int psr_timing_begin(void);
+int psr_timing_end(double* total_ms, int64_t* launches);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* psr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSR_H */

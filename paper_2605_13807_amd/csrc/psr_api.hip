@@ -1,0 +1,578 @@
+// libpsr C ABI: argument checks, parameter/workspace layouts and dispatch.
+// Every compute step runs in the kernels of psr_fwd.hip, psr_ham.hip and
+// psr_bwd.hip; this file only validates, carves the caller's workspace and
+// queues launches on the caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "../../include/psr.h"
+#include "psr_internal.h"
+
+namespace psr {
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int ok() {
+    g_err[0] = 0;
+    return PSR_OK;
+}
+
+static int dev_check(int e, const char* what) {
+    if (e != 0) return fail(PSR_EDEVICE, "%s: HIP error %d (%s)", what, e, hipGetErrorString((hipError_t)e));
+    return PSR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// model checks and layouts
+// ---------------------------------------------------------------------------
+
+static int check_model(const psr_model_desc* m, Geom* out) {
+    if (!m) return fail(PSR_EINVAL, "model descriptor is NULL");
+    if (m->geometry != PSR_CHAIN_1D && m->geometry != PSR_SNAKE_2D)
+        return fail(PSR_EINVAL, "geometry %d is not PSR_CHAIN_1D or PSR_SNAKE_2D", m->geometry);
+    if (m->lx < 1 || m->ly < 1) return fail(PSR_EINVAL, "lattice %d x %d is empty", m->lx, m->ly);
+    if ((int64_t)m->lx * m->ly > 65535) return fail(PSR_EUNSUPPORTED, "more than 65535 sites");
+    if (m->geometry == PSR_CHAIN_1D && (m->ly != 1 || m->n_layers != 1))
+        return fail(PSR_EINVAL, "the chain ansatz needs ly = 1 and n_layers = 1");
+    if (m->n_layers < 1 || m->n_layers > 8) return fail(PSR_EINVAL, "n_layers %d outside [1, 8]", m->n_layers);
+    if (m->d != 32 && m->d != 64 && m->d != 128 && m->d != 256)
+        return fail(PSR_EUNSUPPORTED, "hidden size %d is not 32, 64, 128 or 256", m->d);
+    if (m->precision != PSR_FP32 && m->precision != PSR_BF16)
+        return fail(PSR_EINVAL, "precision %d is not PSR_FP32 or PSR_BF16", m->precision);
+    if (m->ckpt_rows < 0) return fail(PSR_EINVAL, "ckpt_rows must be >= 0");
+    Geom g;
+    g.chain = (m->geometry == PSR_CHAIN_1D);
+    g.lx = m->lx;
+    g.ly = m->ly;
+    g.nl = m->n_layers;
+    g.d = m->d;
+    g.prec = m->precision == PSR_BF16 ? kBF16 : kFP32;
+    const FwdShape sh = fwd_shape(g);
+    if (sh.seqs < 1)
+        return fail(PSR_EUNSUPPORTED, "row length %d exceeds the %d columns of a workgroup at d = %d", g.lx, sh.cols,
+                    g.d);
+    if (out) *out = g;
+    return PSR_OK;
+}
+
+int64_t param_count(const Geom& g) {
+    int64_t off[64];
+    int32_t n = 0;
+    param_offsets(g, off, &n);
+    return off[n];
+}
+
+void param_offsets(const Geom& g, int64_t* off, int32_t* n) {
+    const int64_t d = g.d;
+    int k = 0;
+    int64_t p = 0;
+    auto add = [&](int64_t sz) {
+        off[k++] = p;
+        p += sz;
+    };
+    if (g.chain) {
+        add(d * 2);   // W_z
+        add(d);       // b_z
+        add(d * 2);   // W_h
+        add(d);       // b_h
+    } else {
+        for (int l = 0; l < g.nl; ++l) {
+            const int64_t du = (l == 0) ? 4 : d;
+            add(d * du);          // W_z
+            add(d);               // b_z
+            add(d * (du + d));    // W_h
+            add(d);               // b_h
+            add(d * d);           // C
+            add(d * du);          // D
+        }
+    }
+    add(2 * d);   // W_o
+    add(2);       // b_o
+    off[k] = p;
+    *n = k;
+}
+
+Prepared prepared_layout(const Geom& g) {
+    Prepared pl;
+    const int64_t d = g.d;
+    const int64_t mat = d * d * (g.prec == kBF16 ? 2 : 4);
+    int64_t fb = 0;
+    // absent matrices keep offset 0 (never read) so that pointer arithmetic stays in range
+    for (int l = 0; l < 8; ++l)
+        for (int m = 0; m < 5; ++m) {
+            pl.frag[l][m] = 0;
+            pl.frag_present[l][m] = 0;
+        }
+    if (!g.chain) {
+        for (int l = 0; l < g.nl; ++l) {
+            for (int m = 0; m < 5; ++m) {
+                const bool present = (l == 0) ? (m == 2 || m == 4) : true;
+                if (present) {
+                    pl.frag[l][m] = fb;
+                    pl.frag_present[l][m] = 1;
+                    fb += mat;
+                }
+            }
+        }
+    }
+    pl.frag_bytes = fb > 0 ? fb : 256;
+    int64_t t = 0;
+    pl.t0z = t; t += 9 * d;
+    pl.t0h = t; t += 9 * d;
+    pl.t0d = t; t += 9 * d;
+    for (int l = 0; l < 8; ++l) {
+        pl.bias_z[l] = 0;
+        pl.bias_h[l] = 0;
+    }
+    for (int l = 1; l < g.nl; ++l) {
+        pl.bias_z[l] = t; t += d;
+        pl.bias_h[l] = t; t += d;
+    }
+    pl.head_w = t; t += 2 * d;
+    pl.head_b = t; t += 4;
+    pl.table_floats = t;
+    return pl;
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Workspace carving: a sequence of 256-byte aligned regions.
+struct Carver {
+    uint8_t* base;
+    int64_t used = 0;
+    explicit Carver(void* b) : base(reinterpret_cast<uint8_t*>(b)) {}
+    template <class T>
+    T* take(int64_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += align256(count * (int64_t)sizeof(T));
+        return p;
+    }
+};
+
+static int64_t frontier_seq_bytes(const Geom& g) {
+    return (int64_t)g.nl * g.lx * g.d * (g.prec == kBF16 ? 2 : 4);
+}
+
+// sequences per forward launch for psr_logpsi (bounds the frontier workspace to ~256 MB)
+static int64_t logpsi_chunk(const Geom& g, int64_t B) {
+    const int64_t per = frontier_seq_bytes(g);
+    int64_t c = (256ll << 20) / (per > 0 ? per : 1);
+    if (c < 1024) c = 1024;
+    return B < c ? B : c;
+}
+
+struct LogpsiWs {
+    uint32_t* packed;
+    uint8_t* frag;
+    float* tab;
+    void* frontier;
+    float* hi;
+    float* lo;
+    int64_t chunk;
+};
+
+static int64_t carve_logpsi(const Geom& g, int64_t B, void* ws, LogpsiWs* w) {
+    Carver c(ws);
+    const Prepared pl = prepared_layout(g);
+    const int words = (g.lx * g.ly + 31) / 32;
+    w->chunk = logpsi_chunk(g, B);
+    w->packed = c.take<uint32_t>(B * words);
+    w->frag = c.take<uint8_t>(pl.frag_bytes);
+    w->tab = c.take<float>(pl.table_floats);
+    w->frontier = c.take<uint8_t>(w->chunk * frontier_seq_bytes(g));
+    w->hi = c.take<float>(B);
+    w->lo = c.take<float>(B);
+    return c.used;
+}
+
+struct ElocWs {
+    uint32_t* packed;
+    uint8_t* frag;
+    float* tab;
+    void* frontier;
+    int32_t* n_conn;
+    float* diag;
+    int64_t* offs;
+    uint32_t* desc;
+    float* mel;
+    float *chi, *clo, *shi, *slo;
+};
+
+static int64_t carve_eloc(const Geom& g, int64_t B, int64_t max_conn, int64_t chunk, void* ws, ElocWs* w) {
+    Carver c(ws);
+    const Prepared pl = prepared_layout(g);
+    const int words = (g.lx * g.ly + 31) / 32;
+    const int64_t M = B * max_conn;
+    w->packed = c.take<uint32_t>(B * words);
+    w->frag = c.take<uint8_t>(pl.frag_bytes);
+    w->tab = c.take<float>(pl.table_floats);
+    w->frontier = c.take<uint8_t>(chunk * frontier_seq_bytes(g));
+    w->n_conn = c.take<int32_t>(B);
+    w->diag = c.take<float>(B);
+    w->offs = c.take<int64_t>(B + 1);
+    w->desc = c.take<uint32_t>(2 * M);
+    w->mel = c.take<float>(M);
+    w->chi = c.take<float>(M);
+    w->clo = c.take<float>(M);
+    w->shi = c.take<float>(B);
+    w->slo = c.take<float>(B);
+    return c.used;
+}
+
+struct BwdWs {
+    uint32_t* packed;
+    float* scratch;
+    float* O;
+};
+
+static int64_t carve_bwd(const Geom& g, int ckpt_rows, int64_t B, bool need_O, void* ws, BwdWs* w) {
+    Carver c(ws);
+    const BwdLayout bl = bwd_layout(g, ckpt_rows);
+    const int words = (g.lx * g.ly + 31) / 32;
+    w->packed = c.take<uint32_t>(B * words);
+    w->scratch = c.take<float>(B * bl.ws_per_sample_floats);
+    w->O = need_O ? c.take<float>(B * param_count(g)) : nullptr;
+    return c.used;
+}
+
+static int check_ham(const psr_hamiltonian* H, Ham* out) {
+    if (!H) return fail(PSR_EINVAL, "Hamiltonian descriptor is NULL");
+    if (H->kind != PSR_TFIM && H->kind != PSR_HEISENBERG)
+        return fail(PSR_EINVAL, "Hamiltonian kind %d is not PSR_TFIM or PSR_HEISENBERG", H->kind);
+    if (H->lx < 1 || H->ly < 1) return fail(PSR_EINVAL, "lattice %d x %d is empty", H->lx, H->ly);
+    if ((int64_t)H->lx * H->ly > 65535) return fail(PSR_EUNSUPPORTED, "more than 65535 sites");
+    if (H->pbc != 0) return fail(PSR_EUNSUPPORTED, "periodic boundaries are not supported (the paper uses open ones)");
+    if (!std::isfinite(H->J) || !std::isfinite(H->h)) return fail(PSR_EINVAL, "couplings must be finite");
+    Ham h;
+    h.kind = H->kind == PSR_TFIM ? 0 : 1;
+    h.lx = H->lx;
+    h.ly = H->ly;
+    h.marshall = H->marshall ? 1 : 0;
+    h.J = (float)H->J;
+    h.h = (float)H->h;
+    if (out) *out = h;
+    return PSR_OK;
+}
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Forward-kernel timing (psr_timing_begin / psr_timing_end).
+struct TimingState {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+};
+static thread_local TimingState g_tm;
+
+static void timing_before(hipStream_t st, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!g_tm.on) return;
+    if (g_tm.used == g_tm.ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) {
+            hipEventDestroy(a);
+            return;
+        }
+        g_tm.ev.emplace_back(a, b);
+    }
+    auto& p = g_tm.ev[g_tm.used++];
+    hipEventRecord(p.first, st);
+    *stop = p.second;
+}
+
+static int run_forward(const Geom& g, const Prepared& pl, const uint32_t* packed, const uint32_t* desc,
+                       int64_t q_begin, int64_t q_count, const int64_t* q_total, const uint8_t* frag, const float* tab,
+                       void* frontier, float* hi, float* lo, float* logp_site, hipStream_t st) {
+    FwdArgs a;
+    a.g = g;
+    a.spins = packed;
+    a.words_per_seq = (g.lx * g.ly + 31) / 32;
+    a.desc = desc;
+    a.q_begin = q_begin;
+    a.q_count = q_count;
+    a.q_total = q_total;
+    a.frag = frag;
+    a.tab = tab;
+    a.pl = pl;
+    a.sh = fwd_shape(g);
+    a.frontier = frontier;
+    a.out_hi = hi;
+    a.out_lo = lo;
+    a.logp_site = logp_site;
+    hipEvent_t stop;
+    timing_before(st, &stop);
+    const int e = launch_forward(a, st);
+    if (stop) hipEventRecord(stop, st);
+    return e;
+}
+
+}  // namespace psr
+
+using namespace psr;
+
+extern "C" {
+
+const char* psr_last_error(void) { return g_err; }
+
+int psr_timing_begin(void) {
+    g_tm.on = true;
+    g_tm.used = 0;
+    return ok();
+}
+
+int psr_timing_end(double* total_ms, int64_t* launches) {
+    if (!total_ms || !launches) return fail(PSR_EINVAL, "total_ms and launches must not be NULL");
+    double t = 0.0;
+    int r = PSR_OK;
+    for (size_t k = 0; k < g_tm.used && !r; ++k) {
+        float ms = 0.0f;
+        r = dev_check((int)hipEventSynchronize(g_tm.ev[k].second), "timing sync");
+        if (!r) r = dev_check((int)hipEventElapsedTime(&ms, g_tm.ev[k].first, g_tm.ev[k].second), "timing read");
+        t += ms;
+    }
+    *total_ms = t;
+    *launches = (int64_t)g_tm.used;
+    g_tm.on = false;
+    g_tm.used = 0;
+    return r ? r : ok();
+}
+
+int64_t psr_param_count(const psr_model_desc* m) {
+    Geom g;
+    const int r = check_model(m, &g);
+    if (r) return r;
+    ok();
+    return param_count(g);
+}
+
+int psr_param_offsets(const psr_model_desc* m, int64_t* offsets, int32_t* n_tensors) {
+    Geom g;
+    const int r = check_model(m, &g);
+    if (r) return r;
+    if (!offsets || !n_tensors) return fail(PSR_EINVAL, "offsets and n_tensors must not be NULL");
+    int64_t off[64];
+    int32_t n = 0;
+    param_offsets(g, off, &n);
+    for (int k = 0; k <= n; ++k) offsets[k] = off[k];
+    *n_tensors = n;
+    return ok();
+}
+
+int64_t psr_max_connected(const psr_hamiltonian* H) {
+    Ham h;
+    const int r = check_ham(H, &h);
+    if (r) return r;
+    ok();
+    return ham_max_connected(h);
+}
+
+int64_t psr_workspace_bytes(const psr_model_desc* m, int32_t op, int64_t batch, int64_t chunk_seqs) {
+    Geom g;
+    const int r = check_model(m, &g);
+    if (r) return r;
+    if (batch < 0) return fail(PSR_EINVAL, "negative batch");
+    if (chunk_seqs < 0) return fail(PSR_EINVAL, "negative chunk_seqs");
+    ok();
+    if (op == PSR_OP_LOGPSI) {
+        LogpsiWs w;
+        return carve_logpsi(g, batch, nullptr, &w);
+    }
+    if (op == PSR_OP_LOCAL_ENERGY) {
+        psr_hamiltonian H;
+        std::memset(&H, 0, sizeof(H));
+        H.kind = PSR_HEISENBERG;
+        H.lx = g.lx;
+        H.ly = g.ly;
+        Ham h;
+        check_ham(&H, &h);
+        int64_t mc = ham_max_connected(h);
+        if ((int64_t)g.lx * g.ly > mc) mc = (int64_t)g.lx * g.ly;   // enough for either Hamiltonian
+        ElocWs w;
+        const int64_t ch = chunk_seqs > 0 ? chunk_seqs : 32768;
+        return carve_eloc(g, batch, mc, ch, nullptr, &w);
+    }
+    if (op == PSR_OP_BACKWARD) {
+        BwdWs w;
+        return carve_bwd(g, m->ckpt_rows, batch, true, nullptr, &w);
+    }
+    return fail(PSR_EINVAL, "unknown op %d", op);
+}
+
+int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
+               float* logp_site, void* ws, size_t ws_bytes, void* stream) {
+    Geom g;
+    int r = check_model(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !spins || !logpsi) return fail(PSR_EINVAL, "theta, spins and logpsi must not be NULL");
+    LogpsiWs w;
+    const int64_t need = carve_logpsi(g, B, nullptr, &w);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    carve_logpsi(g, B, ws, &w);
+    hipStream_t st = as_stream(stream);
+    const Prepared pl = prepared_layout(g);
+    const int N = g.lx * g.ly;
+    if ((r = dev_check(launch_pack_spins(spins, B, N, w.packed, st), "pack"))) return r;
+    if ((r = dev_check(launch_prepare(g, pl, theta, w.frag, w.tab, st), "prepare"))) return r;
+    for (int64_t q0 = 0; q0 < B; q0 += w.chunk) {
+        const int64_t n = (B - q0 < w.chunk) ? B - q0 : w.chunk;
+        if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, w.hi,
+                                       w.lo, logp_site, st),
+                           "forward")))
+            return r;
+    }
+    if ((r = dev_check(launch_combine_logpsi(w.hi, w.lo, B, logpsi, st), "combine"))) return r;
+    return ok();
+}
+
+int psr_connected(const psr_hamiltonian* H, const int8_t* spins, int64_t B, int64_t max_conn, int8_t* conn,
+                  uint32_t* desc, float* mel, int32_t* n_conn, float* diag, void* stream) {
+    Ham h;
+    int r = check_ham(H, &h);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!spins || !n_conn) return fail(PSR_EINVAL, "spins and n_conn must not be NULL");
+    if (conn && !desc) return fail(PSR_EINVAL, "conn output needs the desc output too");
+    const int64_t need = ham_max_connected(h);
+    if (max_conn < need)
+        return fail(PSR_ECAPACITY, "max_conn %lld is below the %lld connected configurations a sample can have",
+                    (long long)max_conn, (long long)need);
+    hipStream_t st = as_stream(stream);
+    if ((r = dev_check(launch_conn_count(h, spins, B, n_conn, diag, st), "connected count"))) return r;
+    if (desc || mel) {
+        if ((r = dev_check(launch_conn_write(h, spins, B, nullptr, max_conn, desc, mel, st), "connected write")))
+            return r;
+    }
+    if (conn) {
+        if ((r = dev_check(launch_conn_expand(spins, h.lx * h.ly, B, max_conn, n_conn, desc, conn, st),
+                           "connected expand")))
+            return r;
+    }
+    return ok();
+}
+
+int psr_local_energy(const psr_model_desc* m, const float* theta, const psr_hamiltonian* H, const int8_t* spins,
+                     int64_t B, int64_t chunk_seqs, double* eloc, double* stats, float* logpsi, void* ws,
+                     size_t ws_bytes, void* stream) {
+    Geom g;
+    int r = check_model(m, &g);
+    if (r) return r;
+    Ham h;
+    if ((r = check_ham(H, &h))) return r;
+    if (h.lx != g.lx || h.ly != g.ly)
+        return fail(PSR_EINVAL, "Hamiltonian lattice %d x %d differs from the model's %d x %d", h.lx, h.ly, g.lx, g.ly);
+    if (B < 0 || chunk_seqs < 0) return fail(PSR_EINVAL, "negative batch or chunk");
+    if (B == 0) return ok();
+    if (!theta || !spins || !eloc || !stats) return fail(PSR_EINVAL, "theta, spins, eloc and stats must not be NULL");
+    const int64_t chunk = chunk_seqs > 0 ? chunk_seqs : 32768;
+    const int64_t max_conn = ham_max_connected(h);
+    ElocWs w;
+    const int64_t need = carve_eloc(g, B, max_conn, chunk, nullptr, &w);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    carve_eloc(g, B, max_conn, chunk, ws, &w);
+    hipStream_t st = as_stream(stream);
+    const Prepared pl = prepared_layout(g);
+    const int N = g.lx * g.ly;
+    if ((r = dev_check(launch_pack_spins(spins, B, N, w.packed, st), "pack"))) return r;
+    if ((r = dev_check(launch_prepare(g, pl, theta, w.frag, w.tab, st), "prepare"))) return r;
+    if ((r = dev_check(launch_conn_count(h, spins, B, w.n_conn, w.diag, st), "connected count"))) return r;
+    if ((r = dev_check(launch_scan_counts(w.n_conn, B, w.offs, st), "scan"))) return r;
+    if ((r = dev_check(launch_conn_write(h, spins, B, w.offs, 0, w.desc, w.mel, st), "connected write"))) return r;
+    // the samples themselves
+    for (int64_t q0 = 0; q0 < B; q0 += chunk) {
+        const int64_t n = (B - q0 < chunk) ? B - q0 : chunk;
+        if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, w.shi,
+                                       w.slo, nullptr, st),
+                           "forward (samples)")))
+            return r;
+    }
+    // the connected configurations, streamed in chunks; launches past the
+    // device-side total exit at once
+    const int64_t M = B * max_conn;
+    for (int64_t q0 = 0; q0 < M; q0 += chunk) {
+        const int64_t n = (M - q0 < chunk) ? M - q0 : chunk;
+        if ((r = dev_check(run_forward(g, pl, w.packed, w.desc, q0, n, w.offs + B, w.frag, w.tab, w.frontier, w.chi,
+                                       w.clo, nullptr, st),
+                           "forward (connected)")))
+            return r;
+    }
+    if ((r = dev_check(launch_eloc_combine(B, w.offs, w.diag, w.mel, w.chi, w.clo, w.shi, w.slo, eloc, st), "E_loc")))
+        return r;
+    if ((r = dev_check(launch_stats(eloc, B, stats, st), "stats"))) return r;
+    if (logpsi && (r = dev_check(launch_combine_logpsi(w.shi, w.slo, B, logpsi, st), "combine"))) return r;
+    return ok();
+}
+
+int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B, float* O,
+                        float* logpsi, const double* w, double* gout, void* ws, size_t ws_bytes, void* stream) {
+    Geom g;
+    int r = check_model(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !spins) return fail(PSR_EINVAL, "theta and spins must not be NULL");
+    if ((w == nullptr) != (gout == nullptr)) return fail(PSR_EINVAL, "w and g must be both set or both NULL");
+    if (!O && !gout) return fail(PSR_EINVAL, "nothing to compute: O and g are both NULL");
+    BwdWs bw;
+    const int64_t need = carve_bwd(g, m->ckpt_rows, B, O == nullptr, nullptr, &bw);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    carve_bwd(g, m->ckpt_rows, B, O == nullptr, ws, &bw);
+    hipStream_t st = as_stream(stream);
+    const int N = g.lx * g.ly;
+    const int words = (N + 31) / 32;
+    float* Ouse = O ? O : bw.O;
+    const BwdLayout bl = bwd_layout(g, m->ckpt_rows);
+    if ((r = dev_check(launch_pack_spins(spins, B, N, bw.packed, st), "pack"))) return r;
+    if ((r = dev_check(launch_backward(g, bl, theta, bw.packed, words, B, nullptr, bw.scratch, Ouse, logpsi, st),
+                       "backward")))
+        return r;
+    if (gout && (r = dev_check(launch_weighted_sum(Ouse, B, param_count(g), w, gout, st), "gradient sum"))) return r;
+    return ok();
+}
+
+int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, void* stream) {
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!eloc || !stats || !w) return fail(PSR_EINVAL, "eloc, stats and w must not be NULL");
+    int r;
+    if ((r = dev_check(launch_vmc_weights(eloc, stats, B, w, as_stream(stream)), "weights"))) return r;
+    return ok();
+}
+
+int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream) {
+    if (n_values < 0) return fail(PSR_EINVAL, "negative size");
+    if (n_values == 0) return ok();
+    if (!spins) return fail(PSR_EINVAL, "spins must not be NULL");
+    int* bad = nullptr;
+    int r;
+    if ((r = dev_check((int)hipMalloc(&bad, sizeof(int)), "allocate flag"))) return r;
+    hipStream_t st = as_stream(stream);
+    int host = 0;
+    r = dev_check(launch_check_spins(spins, n_values, bad, st), "check");
+    if (!r) r = dev_check((int)hipMemcpyAsync(&host, bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
+    if (!r) r = dev_check((int)hipStreamSynchronize(st), "synchronise");
+    hipFree(bad);
+    if (r) return r;
+    if (host) return fail(PSR_EDATA, "spins outside {0, 1}");
+    return ok();
+}
+
+}  // extern "C"

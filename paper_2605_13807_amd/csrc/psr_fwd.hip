@@ -1,0 +1,634 @@
+// Forward evaluation of log psi for the 1D minGRU chain (Sec. II.C) and the
+// stacked 2D snake minGRU (Sec. II.F-G), on gfx950.
+//
+// One workgroup = 4 waves; each wave owns NTC tiles of 16 columns, a column
+// being one (sequence, site-in-row) pair.  Sequences are packed back to back
+// along the workgroup's columns (a sequence row may straddle tiles and waves).
+// Rows are processed one after the other (the vertical input h_V makes rows
+// sequential, Sec. II.F); inside a row, for every layer:
+//   1. projections  z_pre = W_z u + b_z,  htilde = W_h [u, h_V] + b_h
+//      on MFMA (layer 0: the u-part is a gather from 9-entry tables, because
+//      u^(0) is two one-hot spins or zeros);
+//   2. gates a = z, b = (1 - z) htilde, and the affine recurrence
+//      h_t = a_t h_{t-1} + b_t along the row as a chunked parallel scan:
+//      Hillis-Steele over the 16 lanes of a DPP row, then a carry chain across
+//      the wave's tiles, then (if a row straddles waves) across waves through LDS.
+//      A row start has a = 0, which is how h_H = 0 outside the lattice enters
+//      and how packed sequences stay independent (segmented scan);
+//   3. h is written to the row frontier (global workspace, read as h_V by the
+//      next row) and x = GELU(C h + D u + s) is formed on MFMA;
+//   4. after the last layer, the head gives log p of the site's own spin,
+//      accumulated per column with compensated (Neumaier) summation.
+#include "psr_internal.h"
+
+namespace psr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int P> struct MF;
+template <> struct MF<kBF16> {
+    typedef bf16x8 Frag;
+    static constexpr int K = 32;
+    static constexpr int ELT = 2;
+    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MF<kFP32> {
+    typedef float Frag;
+    static constexpr int K = 4;
+    static constexpr int ELT = 4;
+    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Parameter preparation: fragment-order weights and slot-order tables
+// ---------------------------------------------------------------------------
+
+__device__ __host__ inline int unit_pos(int u, int d) {
+    // position of unit u in a slot-ordered vector: [g][s], unit = slot_unit(s, g)
+    return ((u >> 2) & 3) * (d >> 2) + 4 * (u >> 4) + (u & 3);
+}
+
+__global__ void prep_frag_bf16(const float* __restrict__ theta, MatSrc src, int d, __bf16* __restrict__ out) {
+    const int64_t n = (int64_t)d * d;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e & 7);
+    const int lane = (int)((e >> 3) & 63);
+    const int64_t f = e >> 9;             // fragment index = mt * (d/32) + kb
+    const int nkb = d / 32;
+    const int kb = (int)(f % nkb), mt = (int)(f / nkb);
+    const int r = 16 * mt + (lane & 15), g = lane >> 4;
+    const int k = slot_unit(8 * kb + j, g);
+    out[e] = (__bf16)theta[src.base + (int64_t)r * src.ld + src.coff + k];
+}
+
+__global__ void prep_frag_f32(const float* __restrict__ theta, MatSrc src, int d, float* __restrict__ out) {
+    const int64_t n = (int64_t)d * d;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ee = (int)(e & 3);
+    const int lane = (int)((e >> 2) & 63);
+    const int64_t f = e >> 8;             // mt * (d/16) + kq
+    const int nkq = d / 16;
+    const int kq = (int)(f % nkq), mt = (int)(f / nkq);
+    const int r = 16 * mt + (lane & 15), g = lane >> 4;
+    const int k = slot_unit(4 * kq + ee, g);
+    out[e] = theta[src.base + (int64_t)r * src.ld + src.coff + k];
+}
+
+// Layer-0 gathers.  state = 3*sH + sV with s = spin value or 2 (outside).
+// snake: u^(0) = [onehot(sH), onehot(sV)];  chain: u^(0) = onehot(sH).
+struct Tab0Src {
+    int chain, d;
+    int64_t wz, bz, wh, bh, dd;   // theta offsets of W_z^(0), b_z^(0), W_h^(0), b_h^(0), D^(0) (dd < 0: none)
+    int ldz, ldh;                 // row strides of W_z^(0) and W_h^(0)
+};
+
+__global__ void prep_tab0(const float* __restrict__ theta, Tab0Src s, float* __restrict__ tz, float* __restrict__ th,
+                          float* __restrict__ td) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 9 * s.d) return;
+    const int st = e / s.d, u = e % s.d;
+    const int sH = st / 3, sV = st % 3;
+    float z = theta[s.bz + u], h = theta[s.bh + u], dv = 0.0f;
+    if (sH < 2) {
+        z += theta[s.wz + (int64_t)u * s.ldz + sH];
+        h += theta[s.wh + (int64_t)u * s.ldh + sH];
+        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * 4 + sH];
+    }
+    if (!s.chain && sV < 2) {
+        z += theta[s.wz + (int64_t)u * s.ldz + 2 + sV];
+        h += theta[s.wh + (int64_t)u * s.ldh + 2 + sV];
+        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * 4 + 2 + sV];
+    }
+    const int p = st * s.d + unit_pos(u, s.d);
+    tz[p] = z;
+    th[p] = h;
+    td[p] = dv;
+}
+
+__global__ void prep_vec(const float* __restrict__ theta, int64_t src, int d, int rows, float* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * d) return;
+    const int r = e / d, u = e % d;
+    out[r * d + unit_pos(u, d)] = theta[src + e];
+}
+
+int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_t* frag, float* tab, hipStream_t st) {
+    const int d = g.d;
+    int64_t off[64];
+    int32_t nt = 0;
+    param_offsets(g, off, &nt);
+    const int T = 256;
+    // fragments
+    for (int l = 0; l < g.nl; ++l) {
+        for (int m = 0; m < 5; ++m) {
+            if (!pl.frag_present[l][m]) continue;
+            const int64_t fo = pl.frag[l][m];
+            // tensor order per layer: W_z, b_z, W_h, b_h, C, D
+            const int64_t wz = off[6 * l + 0], wh = off[6 * l + 2], cc = off[6 * l + 4], dd = off[6 * l + 5];
+            const int du = (l == 0) ? 4 : d;
+            MatSrc s;
+            switch (m) {
+                case 0: s = MatSrc{wz, du, 0}; break;
+                case 1: s = MatSrc{wh, du + d, 0}; break;
+                case 2: s = MatSrc{wh, du + d, du}; break;
+                case 3: s = MatSrc{dd, du, 0}; break;
+                default: s = MatSrc{cc, d, 0}; break;
+            }
+            const int64_t n = (int64_t)d * d;
+            const int blocks = (int)((n + T - 1) / T);
+            if (g.prec == kBF16)
+                prep_frag_bf16<<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<__bf16*>(frag + fo));
+            else
+                prep_frag_f32<<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<float*>(frag + fo));
+        }
+    }
+    // layer-0 tables
+    Tab0Src s0;
+    s0.chain = g.chain;
+    s0.d = d;
+    s0.wz = off[0];
+    s0.bz = off[1];
+    s0.wh = off[2];
+    s0.bh = off[3];
+    if (g.chain) {
+        s0.dd = -1;
+        s0.ldz = 2;
+        s0.ldh = 2;
+    } else {
+        s0.dd = off[5];
+        s0.ldz = 4;
+        s0.ldh = 4 + d;
+    }
+    prep_tab0<<<(9 * d + T - 1) / T, T, 0, st>>>(theta, s0, tab + pl.t0z, tab + pl.t0h, tab + pl.t0d);
+    for (int l = 1; l < g.nl; ++l) {
+        prep_vec<<<(d + T - 1) / T, T, 0, st>>>(theta, off[6 * l + 1], d, 1, tab + pl.bias_z[l]);
+        prep_vec<<<(d + T - 1) / T, T, 0, st>>>(theta, off[6 * l + 3], d, 1, tab + pl.bias_h[l]);
+    }
+    const int ih = g.chain ? 4 : 6 * g.nl;   // index of W_o in the tensor list
+    prep_vec<<<(2 * d + T - 1) / T, T, 0, st>>>(theta, off[ih], d, 2, tab + pl.head_w);
+    hipMemcpyAsync(tab + pl.head_b, theta + off[ih + 1], 2 * sizeof(float), hipMemcpyDeviceToDevice, st);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ inline float dpp(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, src), CTRL, 0xf, 0xf,
+                                                                 false));
+}
+
+// Inclusive scan of affine pairs (A, B) over the 16 lanes of each DPP row:
+// (A, B) at lane i becomes the composition of lanes 0..i, applied in order.
+__device__ inline void row_scan(float& A, float& B) {
+    float a, b;
+    a = dpp<0x111>(1.0f, A); b = dpp<0x111>(0.0f, B); B = fmaf(A, b, B); A *= a;
+    a = dpp<0x112>(1.0f, A); b = dpp<0x112>(0.0f, B); B = fmaf(A, b, B); A *= a;
+    a = dpp<0x114>(1.0f, A); b = dpp<0x114>(0.0f, B); B = fmaf(A, b, B); A *= a;
+    a = dpp<0x118>(1.0f, A); b = dpp<0x118>(0.0f, B); B = fmaf(A, b, B); A *= a;
+}
+
+// value of lane 15 of the lane's DPP row
+__device__ inline float bcast15(float v) { return dpp<0x15F>(0.0f, v); }
+
+__device__ inline float gelu_erf(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ inline void neumaier(float& s, float& c, float v) {
+    const float t = s + v;
+    c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
+    s = t;
+}
+
+template <int P, int D, int NTC>
+__device__ inline void mma_tile(f32x4 (&acc)[NTC], const uint8_t* __restrict__ mat, int mt,
+                                const typename MF<P>::Frag (&b)[NTC][D / MF<P>::K], int lane) {
+    if constexpr (P == kBF16) {
+        const bf16x8* A = reinterpret_cast<const bf16x8*>(mat) + (size_t)mt * (D / 32) * 64 + lane;
+#pragma unroll
+        for (int kb = 0; kb < D / 32; ++kb) {
+            const bf16x8 a = A[kb * 64];
+#pragma unroll
+            for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(a, b[c][kb], acc[c]);
+        }
+    } else {
+        const f32x4* A = reinterpret_cast<const f32x4*>(mat) + (size_t)mt * (D / 16) * 64 + lane;
+#pragma unroll
+        for (int kq = 0; kq < D / 16; ++kq) {
+            const f32x4 a = A[kq * 64];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(a[e], b[c][4 * kq + e], acc[c]);
+            }
+        }
+    }
+}
+
+template <int P, int D>
+__device__ inline void set_slot(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, float x) {
+    if constexpr (P == kBF16)
+        f[s >> 3][s & 7] = (__bf16)x;
+    else
+        f[s] = x;
+}
+
+// frontier element pointer: sequence-local index qi, layer l, physical column i, lane group g
+template <int P, int D>
+__device__ inline uint8_t* fr_ptr(void* base, int64_t qi, int l, int nl, int lx, int i, int g) {
+    return reinterpret_cast<uint8_t*>(base) +
+           ((((size_t)qi * nl + l) * lx + i) * D + (size_t)g * (D / 4)) * MF<P>::ELT;
+}
+
+template <int P, int D, int NTC>
+__device__ inline void load_frontier(typename MF<P>::Frag (&hv)[NTC][D / MF<P>::K], const uint8_t* const (&ptr)[NTC],
+                                     const bool (&ok)[NTC]) {
+#pragma unroll
+    for (int c = 0; c < NTC; ++c) {
+        if constexpr (P == kBF16) {
+            const bf16x8* s = reinterpret_cast<const bf16x8*>(ptr[c]);
+#pragma unroll
+            for (int kb = 0; kb < D / 32; ++kb) hv[c][kb] = ok[c] ? s[kb] : bf16x8{};
+        } else {
+            const f32x4* s = reinterpret_cast<const f32x4*>(ptr[c]);
+#pragma unroll
+            for (int q = 0; q < D / 16; ++q) {
+                const f32x4 v = ok[c] ? s[q] : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hv[c][4 * q + e] = v[e];
+            }
+        }
+    }
+}
+
+template <int P, int D>
+__device__ inline void store_frontier(uint8_t* ptr, const float (&h)[D / 4]) {
+    if constexpr (P == kBF16) {
+        bf16x8* d = reinterpret_cast<bf16x8*>(ptr);
+#pragma unroll
+        for (int kb = 0; kb < D / 32; ++kb) {
+            bf16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)h[8 * kb + j];
+            d[kb] = v;
+        }
+    } else {
+        f32x4* d = reinterpret_cast<f32x4*>(ptr);
+#pragma unroll
+        for (int q = 0; q < D / 16; ++q) d[q] = f32x4{h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused row-recurrence forward kernel
+// ---------------------------------------------------------------------------
+
+constexpr int kWaves = 4;
+
+template <int P, int D, int NTC>
+__global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
+    using F = MF<P>;
+    typedef typename F::Frag Frag;
+    constexpr int NK = D / F::K;   // B fragments per tile
+    constexpr int NS = D / 4;      // slots per lane
+    constexpr int NMT = D / 16;    // 16-unit output tiles
+    constexpr int COLS = kWaves * NTC * 16;
+
+    __shared__ float xw[2][kWaves][16][2];
+    __shared__ float red[COLS][2];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const Geom G = a.g;
+    const int lx = G.lx, ly = G.ly, nl = G.nl;
+    const int N = lx * ly;
+    const int seqs = a.sh.seqs;
+
+    int64_t q_end = a.q_begin + a.q_count;
+    if (a.q_total) q_end = min(q_end, *a.q_total);
+    const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * seqs;
+    if (q0 >= q_end) return;   // uniform across the workgroup
+
+    // per-column constants
+    int t[NTC];
+    bool valid[NTC], seg0[NTC];
+    int64_t qi[NTC];
+    const uint32_t* sp[NTC];
+    int fa[NTC], fb[NTC];
+#pragma unroll
+    for (int c = 0; c < NTC; ++c) {
+        const int col = (wave * NTC + c) * 16 + r16;
+        const int k = col / lx;
+        t[c] = col - k * lx;
+        const int64_t q = q0 + k;
+        valid[c] = (k < seqs) && (q < q_end);
+        seg0[c] = (t[c] == 0);
+        qi[c] = valid[c] ? (q - a.q_begin) : 0;
+        int64_t row = valid[c] ? q : q0;
+        fa[c] = -1;
+        fb[c] = -1;
+        if (a.desc && valid[c]) {
+            const uint32_t s0 = a.desc[2 * q], s1 = a.desc[2 * q + 1];
+            row = s0;
+            fa[c] = (int)(s1 & 0xFFFF);
+            fb[c] = (int)(s1 >> 16);
+            if (fb[c] == fa[c]) fb[c] = -1;
+        }
+        sp[c] = a.spins + (size_t)row * a.words_per_seq;
+    }
+    auto spin = [&](int c, int site) -> int {
+        const int v = (int)((sp[c][site >> 5] >> (site & 31)) & 1u);
+        return v ^ (int)(site == fa[c]) ^ (int)(site == fb[c]);
+    };
+
+    const float* tab = a.tab;
+    float ls[NTC], lc[NTC];
+#pragma unroll
+    for (int c = 0; c < NTC; ++c) ls[c] = lc[c] = 0.0f;
+
+    Frag u[NTC][NK];      // B operand: input of the current layer (layers >= 1)
+    float hprev[NTC][NS]; // h^(l-1) of this row (residual), later the last layer's x
+
+    for (int j = 0; j < ly; ++j) {
+        __syncthreads();   // frontier of row j-1 is complete
+        int iph[NTC], st[NTC], own[NTC];
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) {
+            const int i = (j & 1) ? (lx - 1 - t[c]) : t[c];
+            iph[c] = i;
+            int sH = 2, sV = 2;
+            const int ih = (j & 1) ? i + 1 : i - 1;
+            if (valid[c]) {
+                if (ih >= 0 && ih < lx) sH = spin(c, j * lx + ih);
+                if (j > 0) sV = spin(c, (j - 1) * lx + i);
+                own[c] = spin(c, j * lx + i);
+            } else {
+                own[c] = 0;
+            }
+            st[c] = 3 * sH + sV;
+        }
+
+        for (int l = 0; l < nl; ++l) {
+            const uint8_t* fz = a.frag + a.pl.frag[l][0];
+            const uint8_t* fhu = a.frag + a.pl.frag[l][1];
+            const uint8_t* fhv = a.frag + a.pl.frag[l][2];
+            const uint8_t* fd = a.frag + a.pl.frag[l][3];
+            const uint8_t* fc = a.frag + a.pl.frag[l][4];
+            const bool vert = (!G.chain) && (j > 0);
+
+            Frag hv[NTC][NK];
+            if (vert) {
+                const uint8_t* ptr[NTC];
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
+                    ptr[c] = fr_ptr<P, D>(a.frontier, qi[c], l, nl, lx, iph[c], g);
+                load_frontier<P, D, NTC>(hv, ptr, valid);
+            }
+
+            float hcur[NTC][NS];
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                f32x4 az[NTC], ah[NTC];
+                if (l == 0) {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        const int o = st[c] * D + g * NS + 4 * mt;
+                        az[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0z + o);
+                        ah[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0h + o);
+                    }
+                } else {
+                    const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l] + g * NS + 4 * mt);
+                    const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l] + g * NS + 4 * mt);
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        az[c] = bz;
+                        ah[c] = bh;
+                    }
+                    mma_tile<P, D, NTC>(az, fz, mt, u, lane);
+                    mma_tile<P, D, NTC>(ah, fhu, mt, u, lane);
+                }
+                if (vert) mma_tile<P, D, NTC>(ah, fhv, mt, hv, lane);
+
+                // gates + chunked scan along the row for the 4 units of this tile
+                float Af[NTC][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        const float zp = fmaxf(az[c][i], -80.0f);
+                        const float e = __expf(-zp);
+                        const float z = __builtin_amdgcn_rcpf(1.0f + e);
+                        float A = z, B = (e * z) * ah[c][i];
+                        if (seg0[c] || !valid[c]) A = 0.0f;
+                        if (!valid[c]) B = 0.0f;
+                        row_scan(A, B);
+                        if (c > 0) {
+                            const float ch = bcast15(hcur[c - 1][4 * mt + i]);
+                            const float ca = bcast15(Af[c - 1][i]);
+                            B = fmaf(A, ch, B);
+                            A *= ca;
+                        }
+                        hcur[c][4 * mt + i] = B;
+                        Af[c][i] = A;
+                    }
+                }
+                if (a.sh.cross_wave) {
+                    const int buf = mt & 1;
+                    if (r16 == 15) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            xw[buf][wave][4 * g + i][0] = Af[NTC - 1][i];
+                            xw[buf][wave][4 * g + i][1] = hcur[NTC - 1][4 * mt + i];
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float X = 0.0f;
+                        for (int w = 0; w < wave; ++w) X = fmaf(xw[buf][w][4 * g + i][0], X, xw[buf][w][4 * g + i][1]);
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) hcur[c][4 * mt + i] = fmaf(Af[c][i], X, hcur[c][4 * mt + i]);
+                    }
+                }
+            }
+
+            // frontier for the next row
+            if (!G.chain && j + 1 < ly) {
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
+                    if (valid[c]) store_frontier<P, D>(fr_ptr<P, D>(a.frontier, qi[c], l, nl, lx, iph[c], g), hcur[c]);
+            }
+
+            if (G.chain) {
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) hprev[c][s] = hcur[c][s];
+                break;
+            }
+
+            // x = GELU(C h + D u + s)
+            Frag hb[NTC][NK];
+#pragma unroll
+            for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) set_slot<P, D>(hb[c], s, hcur[c][s]);
+            Frag xn[NTC][NK];
+            const bool last = (l == nl - 1);
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                f32x4 ao[NTC];
+                if (l == 0) {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+                        ao[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) ao[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    mma_tile<P, D, NTC>(ao, fd, mt, u, lane);
+                }
+                mma_tile<P, D, NTC>(ao, fc, mt, hb, lane);
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float x = ao[c][i];
+                        if (l >= 2) x += hprev[c][4 * mt + i];
+                        x = gelu_erf(x);
+                        if (last)
+                            hprev[c][4 * mt + i] = x;
+                        else
+                            set_slot<P, D>(xn[c], 4 * mt + i, x);
+                    }
+                }
+            }
+            if (!last) {
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) {
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) u[c][k] = xn[c][k];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) hprev[c][s] = hcur[c][s];
+                }
+            }
+        }
+
+        // head: logits = W_o x + b_o on the last layer's output (chain: on h)
+        const float* wo = tab + a.pl.head_w;
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) {
+            float l0 = 0.0f, l1 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NS / 4; ++q) {
+                const f32x4 w0 = *reinterpret_cast<const f32x4*>(wo + g * NS + 4 * q);
+                const f32x4 w1 = *reinterpret_cast<const f32x4*>(wo + D + g * NS + 4 * q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    l0 = fmaf(w0[e], hprev[c][4 * q + e], l0);
+                    l1 = fmaf(w1[e], hprev[c][4 * q + e], l1);
+                }
+            }
+            l0 += __shfl_xor(l0, 16);
+            l1 += __shfl_xor(l1, 16);
+            l0 += __shfl_xor(l0, 32);
+            l1 += __shfl_xor(l1, 32);
+            l0 += tab[a.pl.head_b];
+            l1 += tab[a.pl.head_b + 1];
+            const float dl = own[c] ? (l0 - l1) : (l1 - l0);
+            const float lp = -(fmaxf(dl, 0.0f) + log1pf(expf(-fabsf(dl))));
+            if (valid[c]) {
+                neumaier(ls[c], lc[c], lp);
+                if (a.logp_site && g == 0) a.logp_site[(size_t)(q0 + (( (wave * NTC + c) * 16 + r16) / lx)) * N + j * lx + iph[c]] = lp;
+            }
+        }
+    }
+
+    // per-sequence total over its columns, in column order
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) {
+            const int col = (wave * NTC + c) * 16 + r16;
+            red[col][0] = valid[c] ? ls[c] : 0.0f;
+            red[col][1] = valid[c] ? lc[c] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < seqs && q0 + k < q_end) {
+        float s = 0.0f, cc = 0.0f;
+        for (int t2 = 0; t2 < lx; ++t2) {
+            neumaier(s, cc, red[k * lx + t2][0]);
+            cc += red[k * lx + t2][1];
+        }
+        // log psi = (1/2) sum log p; split into a float pair (hi, lo), exact scaling
+        const float hi = s + cc;
+        const float lo = cc - (hi - s);
+        a.out_hi[q0 + k] = 0.5f * hi;
+        if (a.out_lo) a.out_lo[q0 + k] = 0.5f * lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch shape and dispatch
+// ---------------------------------------------------------------------------
+
+static int ntc_for(int d) {
+    if (d <= 64) return 4;
+    if (d == 128) return 2;
+    return 1;
+}
+
+FwdShape fwd_shape(const Geom& g) {
+    FwdShape s;
+    s.ntc = ntc_for(g.d);
+    s.waves = kWaves;
+    s.cols = s.waves * s.ntc * 16;
+    s.seqs = s.cols / g.lx;
+    const int per_wave = s.ntc * 16;
+    s.cross_wave = 0;
+    for (int k = 0; k < s.seqs; ++k) {
+        const int c0 = k * g.lx, c1 = (k + 1) * g.lx - 1;
+        if (c0 / per_wave != c1 / per_wave) s.cross_wave = 1;
+    }
+    return s;
+}
+
+template <int P, int D, int NTC>
+static int launch_t(const FwdArgs& a, hipStream_t st) {
+    const int64_t blocks = (a.q_count + a.sh.seqs - 1) / a.sh.seqs;
+    if (blocks <= 0) return 0;
+    fwd_kernel<P, D, NTC><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
+    return (int)hipGetLastError();
+}
+
+int launch_forward(const FwdArgs& a, hipStream_t st) {
+    const int d = a.g.d;
+    if (a.g.prec == kBF16) {
+        switch (d) {
+            case 32: return launch_t<kBF16, 32, 4>(a, st);
+            case 64: return launch_t<kBF16, 64, 4>(a, st);
+            case 128: return launch_t<kBF16, 128, 2>(a, st);
+            case 256: return launch_t<kBF16, 256, 1>(a, st);
+        }
+    } else {
+        switch (d) {
+            case 32: return launch_t<kFP32, 32, 4>(a, st);
+            case 64: return launch_t<kFP32, 64, 4>(a, st);
+            case 128: return launch_t<kFP32, 128, 2>(a, st);
+            case 256: return launch_t<kFP32, 256, 1>(a, st);
+        }
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace psr

@@ -1,0 +1,121 @@
+"""The C ABI on the CPU: the library loads, exports every symbol of
+include/psr.h, and rejects bad arguments on the host with the documented codes
+before queuing any GPU work (no compute call reaches a GPU here)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2605_13807_amd as P  # noqa: N813
+    P.lib()
+    return P
+
+
+def test_exports_every_declared_symbol(P):
+    with open(os.path.join(ROOT, "include", "psr.h")) as f:
+        hdr = f.read()
+    names = set(re.findall(r"\b(psr_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 11
+    for n in sorted(names):
+        assert hasattr(P.lib(), n), n
+
+
+def test_param_layout_matches_oracle(P):
+    from oracle import model as OM
+    for geom, lx, ly, nl, d in ((0, 16, 1, 1, 32), (1, 10, 10, 2, 64), (1, 32, 32, 3, 128), (1, 52, 52, 4, 256),
+                                (1, 3, 2, 5, 32)):
+        m = P.Model(geom, lx, ly, nl, d)
+        om = OM.Model("chain" if geom == 0 else "snake2d", lx, ly, nl, d)
+        off = P.param_offsets(m)
+        shapes = OM.tensor_shapes(om)
+        assert len(off) == len(shapes) + 1
+        sizes = [int(np.prod(s)) for _, s in shapes]
+        assert np.array_equal(np.diff(off), sizes)
+        assert P.param_count(m) == OM.n_params(om)
+
+
+def test_max_connected(P):
+    assert P.max_connected(P.Hamiltonian(P.TFIM, 16, 1)) == 16
+    for L in (4, 10, 20, 32, 52):
+        assert P.max_connected(P.Hamiltonian(P.HEISENBERG, L, L)) == 2 * L * (L - 1)
+    assert P.max_connected(P.Hamiltonian(P.HEISENBERG, 5, 3)) == 4 * 3 + 5 * 2
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(geometry=7), -1),
+    (dict(lx=0), -1),
+    (dict(d=48), -2),
+    (dict(n_layers=0), -1),
+    (dict(n_layers=9), -1),
+    (dict(precision=3), -1),
+    (dict(ckpt_rows=-1), -1),
+    (dict(lx=300, ly=300), -2),
+    (dict(lx=70, d=256), -2),   # row longer than a workgroup's columns at d = 256
+])
+def test_model_validation(P, kw, code):
+    base = dict(geometry=1, lx=4, ly=4, n_layers=2, d=32, precision=0, ckpt_rows=0)
+    base.update(kw)
+    m = P.Model(**base)
+    with pytest.raises(P.PsrError) as e:
+        P.param_count(m)
+    assert e.value.code == code
+
+
+def test_chain_shape_rules(P):
+    with pytest.raises(P.PsrError):
+        P.param_count(P.Model(0, 8, 2, 1, 32))
+    with pytest.raises(P.PsrError):
+        P.param_count(P.Model(0, 8, 1, 2, 32))
+
+
+def test_hamiltonian_validation(P):
+    with pytest.raises(P.PsrError) as e:
+        P.max_connected(P.Hamiltonian(1, 4, 4, pbc=True))
+    assert e.value.code == -2
+    with pytest.raises(P.PsrError) as e:
+        P.max_connected(P.Hamiltonian(5, 4, 4))
+    assert e.value.code == -1
+
+
+def test_compute_calls_check_arguments_before_any_launch(P):
+    L = P.lib()
+    m = P.Model(1, 4, 4, 2, 32).c()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its host checks
+    # NULL outputs
+    assert L.psr_logpsi(ctypes.byref(m), fake, fake, 4, None, None, fake, 1 << 30, None) == -1
+    # workspace too small
+    assert L.psr_logpsi(ctypes.byref(m), fake, fake, 4, fake, None, fake, 16, None) == -3
+    assert b"workspace" in L.psr_last_error()
+    # negative batch
+    assert L.psr_logpsi(ctypes.byref(m), fake, fake, -1, fake, None, fake, 1 << 30, None) == -1
+    # lattice mismatch between model and Hamiltonian
+    h = P.Hamiltonian(1, 5, 4).c()
+    assert L.psr_local_energy(ctypes.byref(m), fake, ctypes.byref(h), fake, 4, 0, fake, fake, None, fake, 1 << 30,
+                              None) == -1
+    # capacity
+    h4 = P.Hamiltonian(1, 4, 4).c()
+    assert L.psr_connected(ctypes.byref(h4), fake, 4, 3, None, None, None, fake, None, None) == -5
+    # conn without desc
+    assert L.psr_connected(ctypes.byref(h4), fake, 4, 100, fake, None, None, fake, None, None) == -1
+    # backward: w without g, nothing requested
+    assert L.psr_logpsi_backward(ctypes.byref(m), fake, fake, 4, None, None, fake, None, fake, 1 << 30, None) == -1
+    assert L.psr_logpsi_backward(ctypes.byref(m), fake, fake, 4, None, None, None, None, fake, 1 << 30, None) == -1
+    # empty batches are no-ops that succeed
+    assert L.psr_logpsi(ctypes.byref(m), None, None, 0, None, None, None, 0, None) == 0
+    assert L.psr_last_error() == b""
+
+
+def test_workspace_sizes_grow_with_batch(P):
+    m = P.Model(1, 10, 10, 2, 64)
+    for op in (0, 1, 2):
+        a = P.workspace_bytes(m, op, 100, 1000)
+        b = P.workspace_bytes(m, op, 200, 1000)
+        assert 0 < a < b

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP library (through its C ABI) against the float64 oracle.
+
+Tolerances (derived in the design doc from the arithmetic of each path):
+  connected configurations, matrix elements, diagonal   bit-exact
+  FP32 path   max |d log psi| <= 1e-5 + 1e-6 |log psi|  (about 16 float32 ulps of log psi)
+  BF16 path   compared with the oracle's BF16 reading (projection operands
+              rounded to bfloat16, everything else exact):
+              max |d log psi| <= 1e-4 + 2e-5 |log psi|; the difference to the
+              exact float64 model is printed and bounded loosely (it is the
+              model's sensitivity to BF16 quantisation, not kernel error)
+  E_loc       max_s |dE| / max(|E|, 1) <= 1e-4 (FP32), 2e-2 (BF16)
+  gradients   per sample ||dO|| / ||O|| <= 1e-4 (the backward runs in FP32)
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import psr_inputs as I
+from oracle import grad as OG
+from oracle import hamiltonian as OH
+from oracle import model as OM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_13807_amd as P  # noqa: N813
+    P.lib()
+    return P
+
+
+def _omodel(geom, lx, ly, nl, d):
+    return OM.Model("chain" if geom == 0 else "snake2d", lx, ly, nl, d)
+
+
+def _case(P, geom, lx, ly, nl, d, prec, B, seed, ckpt_rows=0, spins="bern"):
+    m = P.Model(geom, lx, ly, nl, d, prec, ckpt_rows)
+    om = _omodel(geom, lx, ly, nl, d)
+    assert P.param_count(m) == OM.n_params(om)
+    th = I.params(OM.n_params(om), d, 1000 + seed)
+    N = lx * ly
+    if spins == "bern":
+        s = I.spins_bernoulli(B, N, 2000 + seed)
+    elif spins == "zero":
+        s = I.spins_zero_mag(B, N, 2000 + seed)
+    else:
+        s = I.spins_neel_like(B, lx, ly, 2000 + seed)
+    return m, om, th, s
+
+
+def _tol(prec, ref):
+    scale = float(np.abs(ref).max())
+    return (1e-5 + 1e-6 * scale) if prec == 0 else (1e-4 + 2e-5 * scale)
+
+
+# ----------------------------------------------------------------------------
+# connected configurations: bit-exact
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,lx,ly,spins", [
+    (0, 16, 1, "bern"),          # TFIM chain
+    (1, 10, 10, "zero"),
+    (1, 4, 3, "bern"),
+    (1, 3, 5, "bern"),
+    (1, 1, 6, "bern"),
+    (1, 7, 1, "bern"),
+    (1, 32, 32, "neel"),
+])
+def test_connected_bit_exact(P, kind, lx, ly, spins):
+    B = 37
+    N = lx * ly
+    if spins == "bern":
+        s = I.spins_bernoulli(B, N, 5)
+    elif spins == "zero":
+        s = I.spins_zero_mag(B, N, 5)
+    else:
+        s = I.spins_neel_like(B, lx, ly, 5)
+    oh = OH.Hamiltonian("tfim" if kind == 0 else "heisenberg", lx, ly, J=1.25, h=0.75)
+    ref = OH.connected(oh, s)
+    h = P.Hamiltonian(kind, lx, ly, J=1.25, h=0.75)
+    got = P.connected(h, torch.from_numpy(s).cuda(), configs=True)
+    n = got["n_conn"].cpu().numpy()
+    assert np.array_equal(n, ref["n_conn"])
+    assert np.array_equal(got["diag"].cpu().numpy().astype(np.float64), ref["diag"])
+    desc = got["desc"].cpu().numpy().view(np.uint32)
+    mel = got["mel"].cpu().numpy()
+    conn = got["conn"].cpu().numpy()
+    flips = OH.apply_flips(s, ref)
+    off = 0
+    for b in range(B):
+        k = n[b]
+        assert np.array_equal(desc[b, :k, 0], np.full(k, b, np.uint32))
+        assert np.array_equal(desc[b, :k, 1] & 0xFFFF, ref["a"][off: off + k])
+        assert np.array_equal(desc[b, :k, 1] >> 16, ref["b"][off: off + k])
+        assert np.array_equal(mel[b, :k].astype(np.float64), ref["mel"][off: off + k])
+        assert np.array_equal(conn[b, :k], flips[off: off + k])
+        off += k
+
+
+def test_connected_capacity_error(P):
+    h = P.Hamiltonian(1, 4, 4)
+    s = torch.zeros(2, 16, dtype=torch.int8, device="cuda")
+    with pytest.raises(P.PsrError) as e:
+        P.connected(h, s, max_conn=5)
+    assert e.value.code == -5
+
+
+# ----------------------------------------------------------------------------
+# log psi
+# ----------------------------------------------------------------------------
+
+LOGPSI_CASES = [
+    # geom, lx, ly, nl, d, prec, B
+    (0, 16, 1, 1, 32, 0, 512),     # the 16-site chain workload
+    (0, 16, 1, 1, 32, 1, 77),
+    (1, 4, 4, 3, 32, 0, 100),      # three layers: residual active
+    (1, 5, 3, 2, 64, 0, 61),       # odd width, ragged batch
+    (1, 10, 10, 2, 64, 0, 200),    # the 10x10 workload shape
+    (1, 10, 10, 2, 64, 1, 200),
+    (1, 1, 7, 2, 32, 0, 33),       # one column
+    (1, 9, 1, 3, 32, 0, 33),       # one row
+    (1, 20, 20, 3, 128, 0, 24),    # rows straddle waves
+    (1, 20, 20, 3, 128, 1, 24),
+    (1, 32, 32, 3, 128, 0, 9),
+    (1, 32, 32, 3, 128, 1, 9),
+    (1, 52, 52, 4, 256, 0, 2),     # the largest lattice
+    (1, 52, 52, 4, 256, 1, 2),
+]
+
+
+@pytest.mark.parametrize("geom,lx,ly,nl,d,prec,B", LOGPSI_CASES)
+def test_logpsi_parity(P, geom, lx, ly, nl, d, prec, B):
+    print(f"logpsi case geom={geom} {lx}x{ly} nl={nl} d={d} prec={prec} B={B}", flush=True)
+    m, om, th, s = _case(P, geom, lx, ly, nl, d, prec, B, seed=lx + 3 * ly + d)
+    ref_site, _ = OM.forward(th, s, om, bf16=(prec == 1))
+    ref = 0.5 * ref_site.sum(axis=1)
+    got, site = P.logpsi(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda(), site_logp=True)
+    got = got.cpu().numpy().astype(np.float64)
+    site = site.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max()
+    serr = np.abs(site - ref_site).max()
+    print(f"  max|dlogpsi| = {err:.3e} (tol {_tol(prec, ref):.3e}); max site err {serr:.3e}")
+    assert err <= _tol(prec, ref)
+    assert serr <= (2e-5 if prec == 0 else 2e-3)
+    if prec == 1:
+        exact = OM.logpsi(th, s, om)
+        dev = np.abs(got - exact).max()
+        print(f"  BF16 vs exact float64 model: max|dlogpsi| = {dev:.3e} (|log psi| ~ {np.abs(exact).max():.1f})")
+        assert dev <= 0.02 * np.abs(exact).max()
+
+
+def test_logpsi_determinism_and_batch_invariance(P):
+    m, om, th, s = _case(P, 1, 10, 10, 2, 64, 0, 90, seed=9)
+    tt = torch.from_numpy(th).cuda()
+    ss = torch.from_numpy(s).cuda()
+    a = P.logpsi(m, tt, ss)
+    b = P.logpsi(m, tt, ss)
+    assert torch.equal(a, b)
+    # the same configurations at other batch positions: same values up to the
+    # reassociation of the in-row scan (a different column offset in its tile)
+    perm = torch.randperm(90, generator=torch.Generator().manual_seed(0))
+    c = P.logpsi(m, tt, ss[perm.cuda()])
+    assert (c - a[perm.cuda()]).abs().max().item() <= 2e-5
+
+
+def test_logpsi_empty_batch(P):
+    m = P.Model(1, 4, 4, 2, 32)
+    th = torch.zeros(P.param_count(m), dtype=torch.float32, device="cuda")
+    out = P.logpsi(m, th, torch.zeros(0, 16, dtype=torch.int8, device="cuda"))
+    assert out.numel() == 0
+
+
+def test_logpsi_zero_theta_is_uniform(P):
+    for geom, lx, ly, nl, d in ((0, 16, 1, 1, 32), (1, 6, 5, 3, 64)):
+        m = P.Model(geom, lx, ly, nl, d)
+        th = torch.zeros(P.param_count(m), dtype=torch.float32, device="cuda")
+        s = torch.from_numpy(I.spins_bernoulli(40, lx * ly, 1)).cuda()
+        out = P.logpsi(m, th, s).cpu().numpy()
+        assert np.abs(out + 0.5 * lx * ly * math.log(2)).max() < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# local energy
+# ----------------------------------------------------------------------------
+
+ELOC_CASES = [
+    # geom, lx, ly, nl, d, prec, kind, B, spins, chunk
+    (0, 16, 1, 1, 32, 0, 0, 512, "bern", 32768),   # 16-site TFIM chain workload
+    (1, 10, 10, 2, 64, 0, 1, 48, "zero", 1000),    # 10x10 Heisenberg, several chunks
+    (1, 10, 10, 2, 64, 1, 1, 48, "zero", 32768),
+    (1, 4, 3, 3, 32, 0, 1, 20, "bern", 7),         # tiny chunks, ragged
+    (1, 6, 4, 2, 32, 0, 0, 16, "bern", 32768),     # 2D TFIM
+]
+
+
+@pytest.mark.parametrize("geom,lx,ly,nl,d,prec,kind,B,spins,chunk", ELOC_CASES)
+def test_local_energy_parity(P, geom, lx, ly, nl, d, prec, kind, B, spins, chunk):
+    print(f"eloc case {lx}x{ly} nl={nl} d={d} prec={prec} kind={kind} B={B} chunk={chunk}", flush=True)
+    m, om, th, s = _case(P, geom, lx, ly, nl, d, prec, B, seed=7 + lx, spins=spins)
+    oh = OH.Hamiltonian("tfim" if kind == 0 else "heisenberg", lx, ly, J=1.0, h=1.0)
+    ref = OH.local_energy(lambda c: OM.logpsi(th, c, om, bf16=(prec == 1)), oh, s)
+    h = P.Hamiltonian(kind, lx, ly, J=1.0, h=1.0)
+    e, st, lp = P.local_energy(m, torch.from_numpy(th).cuda(), h, torch.from_numpy(s).cuda(), chunk_seqs=chunk)
+    e = e.cpu().numpy()
+    st = st.cpu().numpy()
+    rel = np.abs(e - ref) / np.maximum(np.abs(ref), 1.0)
+    print(f"  max rel E_loc err {rel.max():.3e}; mean {st[0]:.6f} vs {ref.mean():.6f}")
+    assert rel.max() <= (1e-4 if prec == 0 else 1e-3)
+    mean, var = OG.energy_stats(ref)
+    assert abs(st[0] - mean) <= (1e-5 if prec == 0 else 1e-4) * max(1.0, abs(mean))
+    assert abs(st[1] - var) <= (1e-4 if prec == 0 else 1e-3) * max(1.0, abs(var))
+    if prec == 1:
+        exact = OH.local_energy(lambda c: OM.logpsi(th, c, om), oh, s)
+        rel_x = np.abs(e - exact) / np.maximum(np.abs(exact), 1.0)
+        print(f"  BF16 vs exact float64 model: max rel E_loc err {rel_x.max():.3e}, mean {abs(e.mean() - exact.mean()):.3e}")
+        assert rel_x.max() <= 5e-2
+    # statistics are exactly those of the returned E_loc (FP64 reduction)
+    assert abs(st[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
+
+
+# ----------------------------------------------------------------------------
+# per-sample gradients and the energy-gradient estimator
+# ----------------------------------------------------------------------------
+
+GRAD_CASES = [
+    # geom, lx, ly, nl, d, prec, B, ckpt_rows
+    (0, 16, 1, 1, 32, 0, 8, 0),
+    (1, 4, 3, 3, 32, 0, 6, 1),      # one row per checkpoint chunk
+    (1, 6, 5, 2, 64, 0, 5, 2),      # ragged last chunk
+    (1, 5, 4, 3, 32, 1, 4, 0),      # BF16 model: gradient still FP32
+]
+
+
+@pytest.mark.parametrize("geom,lx,ly,nl,d,prec,B,ckpt", GRAD_CASES)
+def test_per_sample_gradient(P, geom, lx, ly, nl, d, prec, B, ckpt):
+    print(f"grad case {lx}x{ly} nl={nl} d={d} B={B} ckpt={ckpt}", flush=True)
+    m, om, th, s = _case(P, geom, lx, ly, nl, d, prec, B, seed=31 + lx, ckpt_rows=ckpt)
+    lp_ref, O_ref = OG.per_sample_grad(th, s, om)
+    O, lp, _ = P.logpsi_backward(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda())
+    O = O.cpu().numpy().astype(np.float64)
+    lp = lp.cpu().numpy()
+    assert np.abs(lp - lp_ref).max() <= 1e-5 + 2e-7 * lx * ly
+    rel = np.linalg.norm(O - O_ref, axis=1) / np.linalg.norm(O_ref, axis=1)
+    print(f"  max per-sample rel grad err {rel.max():.3e}")
+    assert rel.max() <= 1e-4
+
+
+def test_gradient_estimator(P):
+    m, om, th, s = _case(P, 1, 4, 4, 2, 32, 0, 24, seed=3, spins="zero")
+    oh = OH.Hamiltonian("heisenberg", 4, 4)
+    e_ref = OH.local_energy(lambda c: OM.logpsi(th, c, om), oh, s)
+    _, O_ref = OG.per_sample_grad(th, s, om)
+    g_ref = OG.gradient_estimate(e_ref, O_ref)
+    tt, ss = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
+    e, st, _ = P.local_energy(m, tt, P.Hamiltonian(1, 4, 4), ss)
+    w = P.vmc_weights(e, st)
+    _, _, g = P.logpsi_backward(m, tt, ss, w=w, want_O=False)
+    g = g.cpu().numpy()
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+
+
+def test_autograd_function(P):
+    m, om, th, s = _case(P, 1, 3, 3, 2, 32, 0, 5, seed=4)
+    tt = torch.from_numpy(th).cuda().requires_grad_(True)
+    out = P.LogPsi.apply(tt, torch.from_numpy(s).cuda(), m)
+    coef = torch.linspace(-1, 1, 5, device="cuda")
+    (out * coef).sum().backward()
+    _, O_ref = OG.per_sample_grad(th, s, om)
+    want = coef.cpu().double().numpy() @ O_ref
+    assert np.linalg.norm(tt.grad.cpu().numpy() - want) <= 1e-4 * np.linalg.norm(want)
+
+
+def test_check_spins(P):
+    good = torch.randint(0, 2, (4, 10), dtype=torch.int8, device="cuda")
+    P.check_spins(good)
+    bad = good.clone()
+    bad[2, 3] = 2
+    with pytest.raises(P.PsrError) as e:
+        P.check_spins(bad)
+    assert e.value.code == -6
