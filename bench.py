@@ -110,8 +110,10 @@ def main() -> int:
         P.timing_begin()
         t0 = time.perf_counter()
         out = None
-        for _ in range(steps):
+        for i in range(steps):
             out = step(m, th, s, H, ws_e, ws_b)
+            torch.cuda.synchronize()
+            print(f"# step {i + 1}/{steps} done at {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fwd_ms, fwd_launches = P.timing_end()

@@ -161,6 +161,8 @@ struct Carver {
     }
 };
 
+// Per-sequence device scratch of the forward kernel: the row frontier h^(l)
+// of every layer (the next row's h_V), in the projections' operand type.
 static int64_t frontier_seq_bytes(const Geom& g) {
     return (int64_t)g.nl * g.lx * g.d * (g.prec == kBF16 ? 2 : 4);
 }

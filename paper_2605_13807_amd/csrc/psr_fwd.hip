@@ -15,11 +15,13 @@
 //      the wave's tiles, then (if a row straddles waves) across waves through LDS.
 //      A row start has a = 0, which is how h_H = 0 outside the lattice enters
 //      and how packed sequences stay independent (segmented scan);
-//   3. h is written to the row frontier (global workspace, read as h_V by the
-//      next row) and x = GELU(C h + D u + s) is formed on MFMA;
+//   3. h is stored as the row frontier (global workspace; read back as the
+//      MFMA operand h_V by the next row) and x = GELU(C h + D u + s) is formed
+//      on MFMA, with the residual rows s kept in LDS;
 //   4. after the last layer, the head gives log p of the site's own spin,
 //      accumulated per column with compensated (Neumaier) summation.
 #include "psr_internal.h"
+#include "gelu_fit.h"
 
 namespace psr {
 
@@ -181,27 +183,46 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
 // Device helpers
 // ---------------------------------------------------------------------------
 
+// Lane value from `row_shr:n` within the 16-lane DPP row; lanes without a
+// source read 0 (bound_ctrl), so the move folds into the consuming VALU op.
 template <int CTRL>
-__device__ inline float dpp(float old, float src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
-                                                                 __builtin_bit_cast(int, src), CTRL, 0xf, 0xf,
-                                                                 false));
+__device__ inline float dpp0(float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, src), CTRL, 0xf, 0xf, true));
 }
 
-// Inclusive scan of affine pairs (A, B) over the 16 lanes of each DPP row:
-// (A, B) at lane i becomes the composition of lanes 0..i, applied in order.
-__device__ inline void row_scan(float& A, float& B) {
-    float a, b;
-    a = dpp<0x111>(1.0f, A); b = dpp<0x111>(0.0f, B); B = fmaf(A, b, B); A *= a;
-    a = dpp<0x112>(1.0f, A); b = dpp<0x112>(0.0f, B); B = fmaf(A, b, B); A *= a;
-    a = dpp<0x114>(1.0f, A); b = dpp<0x114>(0.0f, B); B = fmaf(A, b, B); A *= a;
-    a = dpp<0x118>(1.0f, A); b = dpp<0x118>(0.0f, B); B = fmaf(A, b, B); A *= a;
+// Inclusive scan of affine pairs over the 16 lanes of each DPP row
+// (Hillis-Steele, shifts 1, 2, 4, 8).  A pair maps h -> A h + B and is kept as
+// (al, B) with al = 1 - A, so that a lane with no source contributes the
+// identity (al, B) = (0, 0) through the zero fill:
+//   (A, B) after (A', B')  =  (A A', A B' + B),   al_new = al + al' A.
+__device__ inline void row_scan(float& al, float& B) {
+#define PSR_SCAN_STEP(CTRL)                       \
+    {                                             \
+        const float A = 1.0f - al;                \
+        const float bs = dpp0<CTRL>(B);           \
+        const float as = dpp0<CTRL>(al);          \
+        B = fmaf(A, bs, B);                       \
+        al = fmaf(as, A, al);                     \
+    }
+    PSR_SCAN_STEP(0x111)
+    PSR_SCAN_STEP(0x112)
+    PSR_SCAN_STEP(0x114)
+    PSR_SCAN_STEP(0x118)
+#undef PSR_SCAN_STEP
 }
 
-// value of lane 15 of the lane's DPP row
-__device__ inline float bcast15(float v) { return dpp<0x15F>(0.0f, v); }
-
-__device__ inline float gelu_erf(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) = max(x, 0) - |x| p(x) with the Gaussian tail
+// p(x) = erfc(|x|/sqrt 2)/2 ~ t Ph(t) 2^(-C x^2), t = 1/(1 + S|x|)
+// (coefficients fitted by gen_gelu_fit.py).
+__device__ inline float gelu_tail(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(ax, kGeluS, 1.0f));
+    float q = kGeluP[0];
+#pragma unroll
+    for (int k = 1; k <= PSR_GELU_DEG; ++k) q = fmaf(q, t, kGeluP[k]);
+    const float p = (t * q) * __builtin_amdgcn_exp2f((x * x) * -kGeluC);
+    return fmaf(-ax, p, fmaxf(x, 0.0f));
+}
 
 __device__ inline void neumaier(float& s, float& c, float v) {
     const float t = s + v;
@@ -242,59 +263,54 @@ __device__ inline void set_slot(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, 
         f[s] = x;
 }
 
-// frontier element pointer: sequence-local index qi, layer l, physical column i, lane group g
-template <int P, int D>
-__device__ inline uint8_t* fr_ptr(void* base, int64_t qi, int l, int nl, int lx, int i, int g) {
-    return reinterpret_cast<uint8_t*>(base) +
-           ((((size_t)qi * nl + l) * lx + i) * D + (size_t)g * (D / 4)) * MF<P>::ELT;
+// Row frontier (h of the previous row, the operand type of the projections):
+// per sequence-local index qi, layer l, physical column i, lane group g, the
+// lane's d/4 slots are contiguous, so a lane moves whole 16-byte fragments.
+template <int ELT, int D>
+__device__ inline uint8_t* col_ptr(void* base, int64_t qi, int l, int nslot, int lx, int i, int g) {
+    return reinterpret_cast<uint8_t*>(base) + ((((size_t)qi * nslot + l) * lx + i) * D + (size_t)g * (D / 4)) * ELT;
 }
 
-template <int P, int D, int NTC>
-__device__ inline void load_frontier(typename MF<P>::Frag (&hv)[NTC][D / MF<P>::K], const uint8_t* const (&ptr)[NTC],
-                                     const bool (&ok)[NTC]) {
-#pragma unroll
-    for (int c = 0; c < NTC; ++c) {
-        if constexpr (P == kBF16) {
-            const bf16x8* s = reinterpret_cast<const bf16x8*>(ptr[c]);
-#pragma unroll
-            for (int kb = 0; kb < D / 32; ++kb) hv[c][kb] = ok[c] ? s[kb] : bf16x8{};
-        } else {
-            const f32x4* s = reinterpret_cast<const f32x4*>(ptr[c]);
-#pragma unroll
-            for (int q = 0; q < D / 16; ++q) {
-                const f32x4 v = ok[c] ? s[q] : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) hv[c][4 * q + e] = v[e];
-            }
-        }
-    }
-}
-
+// 16-byte pieces of a lane's operand array (BF16: one fragment; FP32: four slots)
 template <int P, int D>
-__device__ inline void store_frontier(uint8_t* ptr, const float (&h)[D / 4]) {
+__device__ inline void frag_set16(typename MF<P>::Frag (&f)[D / MF<P>::K], int k, f32x4 v) {
     if constexpr (P == kBF16) {
-        bf16x8* d = reinterpret_cast<bf16x8*>(ptr);
-#pragma unroll
-        for (int kb = 0; kb < D / 32; ++kb) {
-            bf16x8 v;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = (__bf16)h[8 * kb + j];
-            d[kb] = v;
-        }
+        f[k] = __builtin_bit_cast(bf16x8, v);
     } else {
-        f32x4* d = reinterpret_cast<f32x4*>(ptr);
 #pragma unroll
-        for (int q = 0; q < D / 16; ++q) d[q] = f32x4{h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]};
+        for (int e = 0; e < 4; ++e) f[4 * k + e] = v[e];
     }
+}
+template <int P, int D>
+__device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K], int k) {
+    if constexpr (P == kBF16)
+        return __builtin_bit_cast(f32x4, f[k]);
+    else
+        return f32x4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
 }
 
 // ---------------------------------------------------------------------------
 // The fused row-recurrence forward kernel
 // ---------------------------------------------------------------------------
+//
+// Column layout.  A wave owns 16 chunks (the 16 lanes of a DPP row; the four
+// DPP rows hold four unit groups of the same columns) of NTC consecutive
+// columns each (its NTC MFMA tiles).  Chunk k of the workgroup = wave*16 + lane%16
+// covers flat columns k*NTC .. k*NTC+NTC-1, and sequences occupy lx consecutive
+// flat columns each (a column = one site of the current row of one sequence,
+// in snake order).  The in-row scan is therefore a chunked parallel scan:
+//   (1) inside a lane, the NTC positions of its chunk are composed in order;
+//   (2) the chunk aggregates are scanned across the 16 lanes with DPP;
+//   (3) if a row continues in the next wave, wave aggregates go through LDS;
+//   (4) each position applies the carry entering its chunk: h = A X + B.
+// A position that starts a row has a = 0 (h_H = 0 outside the lattice), which
+// also keeps sequences that share a chunk or a DPP row independent.
+
 
 constexpr int kWaves = 4;
+constexpr float kNegLog2e = -1.4426950408889634f;
 
-template <int P, int D, int NTC>
+template <int P, int D, int NTC, bool CROSS>
 __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     using F = MF<P>;
     typedef typename F::Frag Frag;
@@ -305,6 +321,9 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
     __shared__ float xw[2][kWaves][16][2];
     __shared__ float red[COLS][2];
+    // residual rows h^(l) of layers l >= 1, double-buffered by layer parity:
+    // [parity][wave][tile][output tile][lane] x 4 floats (16 B per lane, conflict-free)
+    __shared__ f32x4 res[2][kWaves][NTC][NMT][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
@@ -318,45 +337,43 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * seqs;
     if (q0 >= q_end) return;   // uniform across the workgroup
 
-    // per-column constants
-    int t[NTC];
-    bool valid[NTC], seg0[NTC];
-    int64_t qi[NTC];
-    const uint32_t* sp[NTC];
-    int fa[NTC], fb[NTC];
+    // per-column constants (column = chunk position c of this lane), kept in 32-bit fields
+    int t[NTC], kq[NTC], srow[NTC], flip[NTC];
+    bool valid[NTC];
 #pragma unroll
     for (int c = 0; c < NTC; ++c) {
-        const int col = (wave * NTC + c) * 16 + r16;
+        const int col = (wave * 16 + r16) * NTC + c;
         const int k = col / lx;
+        kq[c] = k;
         t[c] = col - k * lx;
         const int64_t q = q0 + k;
         valid[c] = (k < seqs) && (q < q_end);
-        seg0[c] = (t[c] == 0);
-        qi[c] = valid[c] ? (q - a.q_begin) : 0;
-        int64_t row = valid[c] ? q : q0;
-        fa[c] = -1;
-        fb[c] = -1;
+        srow[c] = valid[c] ? (int)q : (int)q0;   // packed row of the spins
+        flip[c] = -1;                             // sites a | b << 16 flipped (0xFFFF: none)
         if (a.desc && valid[c]) {
             const uint32_t s0 = a.desc[2 * q], s1 = a.desc[2 * q + 1];
-            row = s0;
-            fa[c] = (int)(s1 & 0xFFFF);
-            fb[c] = (int)(s1 >> 16);
-            if (fb[c] == fa[c]) fb[c] = -1;
+            srow[c] = (int)s0;
+            const uint32_t fa = s1 & 0xFFFF, fb = s1 >> 16;
+            flip[c] = (int)(fa | ((fb == fa ? 0xFFFFu : fb) << 16));
         }
-        sp[c] = a.spins + (size_t)row * a.words_per_seq;
     }
     auto spin = [&](int c, int site) -> int {
-        const int v = (int)((sp[c][site >> 5] >> (site & 31)) & 1u);
-        return v ^ (int)(site == fa[c]) ^ (int)(site == fb[c]);
+        const uint32_t* w = a.spins + (size_t)srow[c] * a.words_per_seq;
+        const int v = (int)((w[site >> 5] >> (site & 31)) & 1u);
+        const int fa = flip[c] & 0xFFFF, fb = (int)((uint32_t)flip[c] >> 16);
+        return v ^ (int)(site == fa) ^ (int)(site == fb);
     };
+    auto seq_local = [&](int c) -> int64_t { return valid[c] ? (q0 + kq[c] - a.q_begin) : 0; };
+    float keep[NTC];   // 0 at a row start: h_H is zero outside the lattice
+#pragma unroll
+    for (int c = 0; c < NTC; ++c) keep[c] = (t[c] == 0) ? 0.0f : 1.0f;
 
     const float* tab = a.tab;
     float ls[NTC], lc[NTC];
 #pragma unroll
     for (int c = 0; c < NTC; ++c) ls[c] = lc[c] = 0.0f;
 
-    Frag u[NTC][NK];      // B operand: input of the current layer (layers >= 1)
-    float hprev[NTC][NS]; // h^(l-1) of this row (residual), later the last layer's x
+    Frag u[NTC][NK];    // B operand: input of the current layer (layers >= 1)
 
     for (int j = 0; j < ly; ++j) {
         __syncthreads();   // frontier of row j-1 is complete
@@ -367,15 +384,23 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             iph[c] = i;
             int sH = 2, sV = 2;
             const int ih = (j & 1) ? i + 1 : i - 1;
+            own[c] = 0;
             if (valid[c]) {
                 if (ih >= 0 && ih < lx) sH = spin(c, j * lx + ih);
                 if (j > 0) sV = spin(c, (j - 1) * lx + i);
                 own[c] = spin(c, j * lx + i);
-            } else {
-                own[c] = 0;
             }
             st[c] = 3 * sH + sV;
         }
+        const bool vert = (!G.chain) && (j > 0);
+        // this row's frontier columns (layer l adds l*lx*D elements)
+        uint8_t* frow[NTC];
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) frow[c] = col_ptr<F::ELT, D>(a.frontier, seq_local(c), 0, nl, lx, iph[c], g);
+        const size_t fl_stride = (size_t)lx * D * F::ELT;
+        float l0[NTC], l1[NTC];   // head logits, accumulated over the last layer's output tiles
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) l0[c] = l1[c] = 0.0f;
 
         for (int l = 0; l < nl; ++l) {
             const uint8_t* fz = a.frag + a.pl.frag[l][0];
@@ -383,20 +408,22 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             const uint8_t* fhv = a.frag + a.pl.frag[l][2];
             const uint8_t* fd = a.frag + a.pl.frag[l][3];
             const uint8_t* fc = a.frag + a.pl.frag[l][4];
-            const bool vert = (!G.chain) && (j > 0);
+            const bool last = (l == nl - 1);
+            const bool keep_res = (l >= 1) && (l + 1 < nl);   // h^(l) is the residual of layer l+1
 
-            Frag hv[NTC][NK];
+            Frag hv[NTC][NK];   // B operand: h_V of this layer (frontier of the previous row)
             if (vert) {
-                const uint8_t* ptr[NTC];
 #pragma unroll
-                for (int c = 0; c < NTC; ++c)
-                    ptr[c] = fr_ptr<P, D>(a.frontier, qi[c], l, nl, lx, iph[c], g);
-                load_frontier<P, D, NTC>(hv, ptr, valid);
+                for (int c = 0; c < NTC; ++c) {
+                    const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
+#pragma unroll
+                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hv[c], k, src[k]);
+                }
             }
-
-            float hcur[NTC][NS];
+            Frag hb[NTC][NK];
 #pragma unroll
             for (int mt = 0; mt < NMT; ++mt) {
+                // ---- projections z_pre, htilde for output units of tile mt
                 f32x4 az[NTC], ah[NTC];
                 if (l == 0) {
 #pragma unroll
@@ -418,72 +445,76 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 }
                 if (vert) mma_tile<P, D, NTC>(ah, fhv, mt, hv, lane);
 
-                // gates + chunked scan along the row for the 4 units of this tile
-                float Af[NTC][4];
+                // ---- gates and the chunked scan along the row
+                float h[NTC][4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
+                    float A[NTC], Bv[NTC];
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
-                        const float zp = fmaxf(az[c][i], -80.0f);
-                        const float e = __expf(-zp);
-                        const float z = __builtin_amdgcn_rcpf(1.0f + e);
-                        float A = z, B = (e * z) * ah[c][i];
-                        if (seg0[c] || !valid[c]) A = 0.0f;
-                        if (!valid[c]) B = 0.0f;
-                        row_scan(A, B);
-                        if (c > 0) {
-                            const float ch = bcast15(hcur[c - 1][4 * mt + i]);
-                            const float ca = bcast15(Af[c - 1][i]);
-                            B = fmaf(A, ch, B);
-                            A *= ca;
+                        const float z = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(az[c][i] * kNegLog2e));
+                        const float aa = z * keep[c];
+                        const float bb = fmaf(-z, ah[c][i], ah[c][i]);   // (1 - z) htilde
+                        if (c == 0) {
+                            A[c] = aa;
+                            Bv[c] = bb;
+                        } else {
+                            Bv[c] = fmaf(aa, Bv[c - 1], bb);
+                            A[c] = aa * A[c - 1];
                         }
-                        hcur[c][4 * mt + i] = B;
-                        Af[c][i] = A;
                     }
+                    float al = 1.0f - A[NTC - 1], gb = Bv[NTC - 1];
+                    row_scan(al, gb);                   // chunks 0..lane of this DPP row
+                    float X = dpp0<0x111>(gb);          // carry entering this lane's chunk
+                    if constexpr (CROSS) {
+                        const float Xa = 1.0f - dpp0<0x111>(al);
+                        const int buf = (mt * 4 + i) & 1;
+                        if (r16 == 15) {
+                            xw[buf][wave][4 * g + i][0] = 1.0f - al;
+                            xw[buf][wave][4 * g + i][1] = gb;
+                        }
+                        __syncthreads();
+                        float W = 0.0f;
+                        for (int w = 0; w < wave; ++w) W = fmaf(xw[buf][w][4 * g + i][0], W, xw[buf][w][4 * g + i][1]);
+                        X = fmaf(Xa, W, X);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) h[c][i] = fmaf(A[c], X, Bv[c]);
                 }
-                if (a.sh.cross_wave) {
-                    const int buf = mt & 1;
-                    if (r16 == 15) {
+
+                // ---- outputs of tile mt: GEMM2 operand, frontier, residual
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) set_slot<P, D>(hb[c], 4 * mt + i, h[c][i]);
+                    if (!valid[c]) continue;
+                    if (keep_res) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
+                    if (G.chain) {   // head reads h directly
+                        const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                        const f32x4 w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            xw[buf][wave][4 * g + i][0] = Af[NTC - 1][i];
-                            xw[buf][wave][4 * g + i][1] = hcur[NTC - 1][4 * mt + i];
+                            l0[c] = fmaf(w0[i], h[c][i], l0[c]);
+                            l1[c] = fmaf(w1[i], h[c][i], l1[c]);
                         }
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float X = 0.0f;
-                        for (int w = 0; w < wave; ++w) X = fmaf(xw[buf][w][4 * g + i][0], X, xw[buf][w][4 * g + i][1]);
-#pragma unroll
-                        for (int c = 0; c < NTC; ++c) hcur[c][4 * mt + i] = fmaf(Af[c][i], X, hcur[c][4 * mt + i]);
                     }
                 }
             }
+            if (G.chain) break;
 
-            // frontier for the next row
-            if (!G.chain && j + 1 < ly) {
+            // h of this row is the next row's h_V: store whole 16-byte fragments
+            if (j + 1 < ly) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c)
-                    if (valid[c]) store_frontier<P, D>(fr_ptr<P, D>(a.frontier, qi[c], l, nl, lx, iph[c], g), hcur[c]);
+                for (int c = 0; c < NTC; ++c) {
+                    if (!valid[c]) continue;
+                    f32x4* dst = reinterpret_cast<f32x4*>(frow[c] + l * fl_stride);
+#pragma unroll
+                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
+                }
             }
 
-            if (G.chain) {
-#pragma unroll
-                for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) hprev[c][s] = hcur[c][s];
-                break;
-            }
-
-            // x = GELU(C h + D u + s)
-            Frag hb[NTC][NK];
-#pragma unroll
-            for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) set_slot<P, D>(hb[c], s, hcur[c][s]);
+            // ---- x = GELU(C h + D u + s)
             Frag xn[NTC][NK];
-            const bool last = (l == nl - 1);
 #pragma unroll
             for (int mt = 0; mt < NMT; ++mt) {
                 f32x4 ao[NTC];
@@ -497,57 +528,50 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     mma_tile<P, D, NTC>(ao, fd, mt, u, lane);
                 }
                 mma_tile<P, D, NTC>(ao, fc, mt, hb, lane);
+                f32x4 w0, w1;
+                if (last) {
+                    w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                    w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+                }
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
+                    if (l >= 2) ao[c] += res[(l - 1) & 1][wave][c][mt][lane];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        float x = ao[c][i];
-                        if (l >= 2) x += hprev[c][4 * mt + i];
-                        x = gelu_erf(x);
-                        if (last)
-                            hprev[c][4 * mt + i] = x;
-                        else
+                        const float x = gelu_tail(ao[c][i]);
+                        if (last) {
+                            l0[c] = fmaf(w0[i], x, l0[c]);
+                            l1[c] = fmaf(w1[i], x, l1[c]);
+                        } else {
                             set_slot<P, D>(xn[c], 4 * mt + i, x);
+                        }
                     }
                 }
             }
             if (!last) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
+                for (int c = 0; c < NTC; ++c)
 #pragma unroll
                     for (int k = 0; k < NK; ++k) u[c][k] = xn[c][k];
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) hprev[c][s] = hcur[c][s];
-                }
             }
         }
 
-        // head: logits = W_o x + b_o on the last layer's output (chain: on h)
-        const float* wo = tab + a.pl.head_w;
+        // head: logits = W_o x + b_o, log p of the site's own spin
+        const float bo0 = tab[a.pl.head_b], bo1 = tab[a.pl.head_b + 1];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
-            float l0 = 0.0f, l1 = 0.0f;
-#pragma unroll
-            for (int q = 0; q < NS / 4; ++q) {
-                const f32x4 w0 = *reinterpret_cast<const f32x4*>(wo + g * NS + 4 * q);
-                const f32x4 w1 = *reinterpret_cast<const f32x4*>(wo + D + g * NS + 4 * q);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    l0 = fmaf(w0[e], hprev[c][4 * q + e], l0);
-                    l1 = fmaf(w1[e], hprev[c][4 * q + e], l1);
-                }
-            }
-            l0 += __shfl_xor(l0, 16);
-            l1 += __shfl_xor(l1, 16);
-            l0 += __shfl_xor(l0, 32);
-            l1 += __shfl_xor(l1, 32);
-            l0 += tab[a.pl.head_b];
-            l1 += tab[a.pl.head_b + 1];
-            const float dl = own[c] ? (l0 - l1) : (l1 - l0);
-            const float lp = -(fmaxf(dl, 0.0f) + log1pf(expf(-fabsf(dl))));
+            float v0 = l0[c], v1 = l1[c];
+            v0 += __shfl_xor(v0, 16);
+            v1 += __shfl_xor(v1, 16);
+            v0 += __shfl_xor(v0, 32);
+            v1 += __shfl_xor(v1, 32);
+            v0 += bo0;
+            v1 += bo1;
+            const float dl = own[c] ? (v0 - v1) : (v1 - v0);
+            const float lp = -(fmaxf(dl, 0.0f) + log1pf(__expf(-fabsf(dl))));
             if (valid[c]) {
                 neumaier(ls[c], lc[c], lp);
-                if (a.logp_site && g == 0) a.logp_site[(size_t)(q0 + (( (wave * NTC + c) * 16 + r16) / lx)) * N + j * lx + iph[c]] = lp;
+                if (a.logp_site && g == 0) a.logp_site[(size_t)(q0 + kq[c]) * N + j * lx + iph[c]] = lp;
             }
         }
     }
@@ -557,7 +581,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     if (g == 0) {
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
-            const int col = (wave * NTC + c) * 16 + r16;
+            const int col = (wave * 16 + r16) * NTC + c;
             red[col][0] = valid[c] ? ls[c] : 0.0f;
             red[col][1] = valid[c] ? lc[c] : 0.0f;
         }
@@ -570,7 +594,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             neumaier(s, cc, red[k * lx + t2][0]);
             cc += red[k * lx + t2][1];
         }
-        // log psi = (1/2) sum log p; split into a float pair (hi, lo), exact scaling
+        // log psi = (1/2) sum log p; kept as a float pair (hi, lo), scaled exactly
         const float hi = s + cc;
         const float lo = cc - (hi - s);
         a.out_hi[q0 + k] = 0.5f * hi;
@@ -582,15 +606,17 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 // Launch shape and dispatch
 // ---------------------------------------------------------------------------
 
-static int ntc_for(int d) {
-    if (d <= 64) return 4;
-    if (d == 128) return 2;
-    return 1;
+// Tiles per wave, chosen so that the four register-resident operand sets
+// (layer input, h_V, h, next input) fit without spills.
+static int ntc_for(int prec, int d) {
+    if (prec == kBF16) return d <= 64 ? 4 : (d == 128 ? 2 : 1);
+    if (d <= 32) return 4;
+    return d <= 128 ? 2 : 1;
 }
 
 FwdShape fwd_shape(const Geom& g) {
     FwdShape s;
-    s.ntc = ntc_for(g.d);
+    s.ntc = ntc_for(g.prec, g.d);
     s.waves = kWaves;
     s.cols = s.waves * s.ntc * 16;
     s.seqs = s.cols / g.lx;
@@ -607,7 +633,10 @@ template <int P, int D, int NTC>
 static int launch_t(const FwdArgs& a, hipStream_t st) {
     const int64_t blocks = (a.q_count + a.sh.seqs - 1) / a.sh.seqs;
     if (blocks <= 0) return 0;
-    fwd_kernel<P, D, NTC><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
+    if (a.sh.cross_wave)
+        fwd_kernel<P, D, NTC, true><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
+    else
+        fwd_kernel<P, D, NTC, false><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
     return (int)hipGetLastError();
 }
 
@@ -623,7 +652,7 @@ int launch_forward(const FwdArgs& a, hipStream_t st) {
     } else {
         switch (d) {
             case 32: return launch_t<kFP32, 32, 4>(a, st);
-            case 64: return launch_t<kFP32, 64, 4>(a, st);
+            case 64: return launch_t<kFP32, 64, 2>(a, st);
             case 128: return launch_t<kFP32, 128, 2>(a, st);
             case 256: return launch_t<kFP32, 256, 1>(a, st);
         }

@@ -83,7 +83,7 @@ struct FwdArgs {
     const float* tab;         // prepared tables
     Prepared pl;
     FwdShape sh;
-    void* frontier;           // [q_count][nl][lx][d] elements (bf16 or f32), indexed by q - q_begin
+    void* frontier;           // [q_count][nl][lx][d] h of the previous row (bf16 or f32), indexed by q - q_begin
     float* out_hi;            // [.] log psi, high part   (indexed by q)
     float* out_lo;            // [.] log psi, low part    (indexed by q) or NULL
     float* logp_site;         // [q][N] or NULL
