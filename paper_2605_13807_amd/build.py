@@ -29,6 +29,8 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA results in VGPRs (no accumulator-register round trips before the VALU epilogues)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

@@ -29,12 +29,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int P> struct MF;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 template <> struct MF<kBF16> {
-    typedef bf16x8 Frag;
+    typedef u32x4 Frag;            // 8 bfloat16 values as 4 dwords (two per dword)
     static constexpr int K = 32;
     static constexpr int ELT = 2;
-    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    __device__ static inline f32x4 mma(bf16x8 a, Frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
     }
 };
 template <> struct MF<kFP32> {
@@ -175,7 +178,8 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
     }
     const int ih = g.chain ? 4 : 6 * g.nl;   // index of W_o in the tensor list
     prep_vec<<<(2 * d + T - 1) / T, T, 0, st>>>(theta, off[ih], d, 2, tab + pl.head_w);
-    hipMemcpyAsync(tab + pl.head_b, theta + off[ih + 1], 2 * sizeof(float), hipMemcpyDeviceToDevice, st);
+    const hipError_t ce = hipMemcpyAsync(tab + pl.head_b, theta + off[ih + 1], 2 * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (ce != hipSuccess) return (int)ce;
     return (int)hipGetLastError();
 }
 
@@ -255,12 +259,18 @@ __device__ inline void mma_tile(f32x4 (&acc)[NTC], const uint8_t* __restrict__ m
     }
 }
 
+// slots s, s+1 (s even) of a lane's operand array; BF16 packs the pair into one dword
 template <int P, int D>
-__device__ inline void set_slot(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, float x) {
-    if constexpr (P == kBF16)
-        f[s >> 3][s & 7] = (__bf16)x;
-    else
-        f[s] = x;
+__device__ inline void set_pair(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, float x0, float x1) {
+    if constexpr (P == kBF16) {
+        bf16x2 v;
+        v[0] = (__bf16)x0;
+        v[1] = (__bf16)x1;
+        f[s >> 3][(s & 7) >> 1] = __builtin_bit_cast(uint32_t, v);
+    } else {
+        f[s] = x0;
+        f[s + 1] = x1;
+    }
 }
 
 // Row frontier (h of the previous row, the operand type of the projections):
@@ -275,7 +285,7 @@ __device__ inline uint8_t* col_ptr(void* base, int64_t qi, int l, int nslot, int
 template <int P, int D>
 __device__ inline void frag_set16(typename MF<P>::Frag (&f)[D / MF<P>::K], int k, f32x4 v) {
     if constexpr (P == kBF16) {
-        f[k] = __builtin_bit_cast(bf16x8, v);
+        f[k] = __builtin_bit_cast(u32x4, v);
     } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) f[4 * k + e] = v[e];
@@ -485,8 +495,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 // ---- outputs of tile mt: GEMM2 operand, frontier, residual
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) set_slot<P, D>(hb[c], 4 * mt + i, h[c][i]);
+                    set_pair<P, D>(hb[c], 4 * mt, h[c][0], h[c][1]);
+                    set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
                     if (!valid[c]) continue;
                     if (keep_res) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
                     if (G.chain) {   // head reads h directly
@@ -513,46 +523,58 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 }
             }
 
-            // ---- x = GELU(C h + D u + s)
-            Frag xn[NTC][NK];
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                f32x4 ao[NTC];
+            // ---- x = GELU(C h + D u + s): accumulator seeded with the table (layer 0)
+            // or the residual row (layers >= 2); the last layer feeds the head directly
+            auto out_tile = [&](int mt, f32x4 (&ao)[NTC]) {
                 if (l == 0) {
 #pragma unroll
                     for (int c = 0; c < NTC; ++c)
                         ao[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
                 } else {
+                    if (l >= 2) {
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c) ao[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                        for (int c = 0; c < NTC; ++c) ao[c] = res[(l - 1) & 1][wave][c][mt][lane];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) ao[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
                     mma_tile<P, D, NTC>(ao, fd, mt, u, lane);
                 }
                 mma_tile<P, D, NTC>(ao, fc, mt, hb, lane);
-                f32x4 w0, w1;
-                if (last) {
-                    w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                    w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
-                }
+            };
+            if (!last) {
+                Frag xn[NTC][NK];
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
-                    if (l >= 2) ao[c] += res[(l - 1) & 1][wave][c][mt][lane];
+                for (int mt = 0; mt < NMT; ++mt) {
+                    f32x4 ao[NTC];
+                    out_tile(mt, ao);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float x = gelu_tail(ao[c][i]);
-                        if (last) {
-                            l0[c] = fmaf(w0[i], x, l0[c]);
-                            l1[c] = fmaf(w1[i], x, l1[c]);
-                        } else {
-                            set_slot<P, D>(xn[c], 4 * mt + i, x);
-                        }
+                    for (int c = 0; c < NTC; ++c) {
+                        set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[c][0]), gelu_tail(ao[c][1]));
+                        set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[c][2]), gelu_tail(ao[c][3]));
                     }
                 }
-            }
-            if (!last) {
 #pragma unroll
                 for (int c = 0; c < NTC; ++c)
 #pragma unroll
                     for (int k = 0; k < NK; ++k) u[c][k] = xn[c][k];
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < NMT; ++mt) {
+                    f32x4 ao[NTC];
+                    out_tile(mt, ao);
+                    const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                    const f32x4 w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float x = gelu_tail(ao[c][i]);
+                            l0[c] = fmaf(w0[i], x, l0[c]);
+                            l1[c] = fmaf(w1[i], x, l1[c]);
+                        }
+                    }
+                }
             }
         }
 
