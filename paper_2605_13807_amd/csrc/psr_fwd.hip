@@ -23,6 +23,8 @@
 #include "psr_internal.h"
 #include "gelu_fit.h"
 
+#include <type_traits>
+
 namespace psr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -194,24 +196,36 @@ __device__ inline float dpp0(float src) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, src), CTRL, 0xf, 0xf, true));
 }
 
-// Inclusive scan of affine pairs over the 16 lanes of each DPP row
-// (Hillis-Steele, shifts 1, 2, 4, 8).  A pair maps h -> A h + B and is kept as
-// (al, B) with al = 1 - A, so that a lane with no source contributes the
-// identity (al, B) = (0, 0) through the zero fill:
-//   (A, B) after (A', B')  =  (A A', A B' + B),   al_new = al + al' A.
-__device__ inline void row_scan(float& al, float& B) {
-#define PSR_SCAN_STEP(CTRL)                       \
-    {                                             \
-        const float A = 1.0f - al;                \
-        const float bs = dpp0<CTRL>(B);           \
-        const float as = dpp0<CTRL>(al);          \
-        B = fmaf(A, bs, B);                       \
-        al = fmaf(as, A, al);                     \
-    }
-    PSR_SCAN_STEP(0x111)
-    PSR_SCAN_STEP(0x112)
-    PSR_SCAN_STEP(0x114)
-    PSR_SCAN_STEP(0x118)
+// Lane value from `row_shr:n`; lanes without a source read 1.
+template <int CTRL>
+__device__ inline float dpp1(float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, 1.0f),
+                                                                 __builtin_bit_cast(int, src), CTRL, 0xf, 0xf, false));
+}
+
+// Inclusive scan of affine maps h -> A h + B over the 16 lanes of each DPP row
+// (Hillis-Steele, shifts 1, 2, 4, 8) for the four slots of a lane at once:
+//   (A, B) after (A', B')  =  (A A', A B' + B).
+// Each step reads the neighbour's registers as the DPP source operand of the
+// VALU op itself -- B += B' A (v_fmac_f32_dpp), then A *= A' (v_mul_f32_dpp) --
+// so it costs two instructions per map.  Without bound_ctrl a lane whose
+// source lies outside the row is not written, i.e. it composes with the
+// identity map.  Hazards: a DPP read of a VGPR needs two wait states after the
+// VALU write; the leading s_nop covers values written just before the block,
+// inside it every DPP read is at least four instructions after the write, and
+// the trailing s_nop covers DPP reads of A right after the block.
+__device__ inline void row_scan4(float (&A)[4], float (&B)[4]) {
+#define PSR_SCAN_STEP(S)                                                   \
+    "v_fmac_f32_dpp %0, %0, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_fmac_f32_dpp %1, %1, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_fmac_f32_dpp %2, %2, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_fmac_f32_dpp %3, %3, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_mul_f32_dpp %4, %4, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
+    "v_mul_f32_dpp %5, %5, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
+    "v_mul_f32_dpp %6, %6, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
+    "v_mul_f32_dpp %7, %7, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
+    asm volatile("s_nop 1\n" PSR_SCAN_STEP("1") PSR_SCAN_STEP("2") PSR_SCAN_STEP("4") PSR_SCAN_STEP("8") "s_nop 1"
+                 : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
 #undef PSR_SCAN_STEP
 }
 
@@ -225,7 +239,9 @@ __device__ inline float gelu_tail(float x) {
 #pragma unroll
     for (int k = 1; k <= PSR_GELU_DEG; ++k) q = fmaf(q, t, kGeluP[k]);
     const float p = (t * q) * __builtin_amdgcn_exp2f((x * x) * -kGeluC);
-    return fmaf(-ax, p, fmaxf(x, 0.0f));
+    // max(x, 0) on the bit pattern: a negative float is a negative int32
+    const float xp = __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+    return fmaf(-ax, p, xp);
 }
 
 __device__ inline void neumaier(float& s, float& c, float v) {
@@ -234,29 +250,98 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-template <int P, int D, int NTC>
-__device__ inline void mma_tile(f32x4 (&acc)[NTC], const uint8_t* __restrict__ mat, int mt,
-                                const typename MF<P>::Frag (&b)[NTC][D / MF<P>::K], int lane) {
+// A operand (weights) of one 16-row output tile, in 16-byte pieces per lane:
+// BF16 one K-block of 32 per piece, FP32 four K-steps of 4 per piece.
+template <int P, int D>
+struct AOp {
+    static constexpr int N = (P == kBF16) ? D / 32 : D / 16;
+    typedef typename std::conditional<P == kBF16, bf16x8, f32x4>::type T;
+};
+
+template <int P, int D, class W>
+__device__ inline void load_a(W& w, const uint8_t* __restrict__ mat, int mt, int lane) {
+    typedef typename AOp<P, D>::T T;
+    const T* A = reinterpret_cast<const T*>(mat) + (size_t)mt * AOp<P, D>::N * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < AOp<P, D>::N; ++k) w[k] = A[k * 64];
+}
+
+// acc[c] += W(tile) * b[c] for the NTC column tiles
+template <int P, int D, int NTC, class W, class B>
+__device__ inline void mma_a(f32x4 (&acc)[NTC], const W& w, const B& b) {
     if constexpr (P == kBF16) {
-        const bf16x8* A = reinterpret_cast<const bf16x8*>(mat) + (size_t)mt * (D / 32) * 64 + lane;
 #pragma unroll
-        for (int kb = 0; kb < D / 32; ++kb) {
-            const bf16x8 a = A[kb * 64];
+        for (int kb = 0; kb < D / 32; ++kb)
 #pragma unroll
-            for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(a, b[c][kb], acc[c]);
-        }
+            for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(w[kb], b[c][kb], acc[c]);
     } else {
-        const f32x4* A = reinterpret_cast<const f32x4*>(mat) + (size_t)mt * (D / 16) * 64 + lane;
 #pragma unroll
-        for (int kq = 0; kq < D / 16; ++kq) {
-            const f32x4 a = A[kq * 64];
+        for (int kq = 0; kq < D / 16; ++kq)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(a[e], b[c][4 * kq + e], acc[c]);
+                for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(w[kq][e], b[c][4 * kq + e], acc[c]);
+    }
+}
+
+constexpr int kWaves = 4;
+constexpr float kNegLog2e = -1.4426950408889634f;
+
+// Gates and the chunked scan of one output tile (4 units per lane, NTC positions):
+//   z = sigmoid(az), a = z (0 at a row start), b = (1 - z) htilde,
+//   h = a h_prev + b along the row.
+template <int NTC, bool CROSS>
+__device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC], const float (&keep)[NTC],
+                                 float (&h)[NTC][4], float (&xw)[2][kWaves][16][2], int mt, int wave, int g, int r16) {
+    float A[NTC][4], Bv[NTC][4];   // maps of the positions, composed inside the chunk
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) {
+            const float z = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(az[c][i] * kNegLog2e));
+            const float aa = z * keep[c];
+            const float bb = fmaf(-z, ah[c][i], ah[c][i]);   // (1 - z) htilde
+            if (c == 0) {
+                A[c][i] = aa;
+                Bv[c][i] = bb;
+            } else {
+                Bv[c][i] = fmaf(aa, Bv[c - 1][i], bb);
+                A[c][i] = aa * A[c - 1][i];
             }
         }
     }
+    float sA[4], sB[4];   // chunk aggregates -> inclusive over chunks 0..lane of the DPP row
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        sA[i] = A[NTC - 1][i];
+        sB[i] = Bv[NTC - 1][i];
+    }
+    row_scan4(sA, sB);
+    float X[4];   // carry entering this lane's chunk
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = dpp0<0x111>(sB[i]);
+    if constexpr (CROSS) {
+        const int buf = mt & 1;
+        if (r16 == 15) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xw[buf][wave][4 * g + i][0] = sA[i];
+                xw[buf][wave][4 * g + i][1] = sB[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float Xa = dpp1<0x111>(sA[i]);   // product of the multipliers before this chunk
+            float W = 0.0f;                        // carry entering this wave
+            for (int w = 0; w < wave; ++w) W = fmaf(xw[buf][w][4 * g + i][0], W, xw[buf][w][4 * g + i][1]);
+            X[i] = fmaf(Xa, W, X[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) h[c][i] = fmaf(A[c][i], X[i], Bv[c][i]);
 }
 
 // slots s, s+1 (s even) of a lane's operand array; BF16 packs the pair into one dword
@@ -317,13 +402,12 @@ __device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K]
 // also keeps sequences that share a chunk or a DPP row independent.
 
 
-constexpr int kWaves = 4;
-constexpr float kNegLog2e = -1.4426950408889634f;
-
-template <int P, int D, int NTC, bool CROSS>
+template <int P, int D, int NTC, bool CROSS, bool CHAIN>
 __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     using F = MF<P>;
     typedef typename F::Frag Frag;
+    typedef typename AOp<P, D>::T AT;
+    constexpr int NA = AOp<P, D>::N;
     constexpr int NK = D / F::K;   // B fragments per tile
     constexpr int NS = D / 4;      // slots per lane
     constexpr int NMT = D / 16;    // 16-unit output tiles
@@ -384,6 +468,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     for (int c = 0; c < NTC; ++c) ls[c] = lc[c] = 0.0f;
 
     Frag u[NTC][NK];    // B operand: input of the current layer (layers >= 1)
+    const size_t fl_stride = (size_t)lx * D * F::ELT;   // frontier bytes per layer
 
     for (int j = 0; j < ly; ++j) {
         __syncthreads();   // frontier of row j-1 is complete
@@ -402,46 +487,92 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             }
             st[c] = 3 * sH + sV;
         }
-        const bool vert = (!G.chain) && (j > 0);
-        // this row's frontier columns (layer l adds l*lx*D elements)
+        const bool vert = (!CHAIN) && (j > 0);
+        // this row's frontier columns (layer l adds l * fl_stride bytes)
         uint8_t* frow[NTC];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) frow[c] = col_ptr<F::ELT, D>(a.frontier, seq_local(c), 0, nl, lx, iph[c], g);
-        const size_t fl_stride = (size_t)lx * D * F::ELT;
         float l0[NTC], l1[NTC];   // head logits, accumulated over the last layer's output tiles
 #pragma unroll
         for (int c = 0; c < NTC; ++c) l0[c] = l1[c] = 0.0f;
 
-        for (int l = 0; l < nl; ++l) {
-            const uint8_t* fz = a.frag + a.pl.frag[l][0];
-            const uint8_t* fhu = a.frag + a.pl.frag[l][1];
-            const uint8_t* fhv = a.frag + a.pl.frag[l][2];
-            const uint8_t* fd = a.frag + a.pl.frag[l][3];
-            const uint8_t* fc = a.frag + a.pl.frag[l][4];
-            const bool last = (l == nl - 1);
-            const bool keep_res = (l >= 1) && (l + 1 < nl);   // h^(l) is the residual of layer l+1
+        // One layer.  FIRST: u is the one-hot layer-0 input (tables);  LAST: x feeds the head.
+        // Inside a layer there is no branch between the output tiles, and the weight
+        // fragments of the next tile are loaded while the current one is computed.
+        auto layer = [&](auto first_c, auto last_c, int l) {
+            constexpr bool FIRST = decltype(first_c)::value;
+            constexpr bool LAST = decltype(last_c)::value;
+            constexpr bool KEEP_RES = !CHAIN && !FIRST && !LAST;   // h^(l) is the residual of layer l+1
+            constexpr int NM1 = CHAIN ? 0 : (FIRST ? 1 : 3);       // GEMM1 matrices: (W_hV) or (W_z, W_hu, W_hV)
+            constexpr int NM2 = CHAIN ? 0 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
+            const uint8_t* m1[3];
+            const uint8_t* m2[2];
+            if constexpr (FIRST) {
+                m1[0] = m1[1] = m1[2] = a.frag + a.pl.frag[l][2];
+                m2[0] = m2[1] = a.frag + a.pl.frag[l][4];
+            } else {
+                m1[0] = a.frag + a.pl.frag[l][0];
+                m1[1] = a.frag + a.pl.frag[l][1];
+                m1[2] = a.frag + a.pl.frag[l][2];
+                m2[0] = a.frag + a.pl.frag[l][3];
+                m2[1] = a.frag + a.pl.frag[l][4];
+            }
 
-            Frag hv[NTC][NK];   // B operand: h_V of this layer (frontier of the previous row)
-            if (vert) {
+            Frag hv[NTC][NK];   // B operand: h_V of this layer (frontier of the previous row; 0 on row 0)
+            if constexpr (!CHAIN) {
+                if (vert) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
-                    const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
+                    for (int c = 0; c < NTC; ++c) {
+                        const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
 #pragma unroll
-                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hv[c], k, src[k]);
+                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hv[c], k, src[k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k)
+                            frag_set16<P, D>(hv[c], k, f32x4{0.f, 0.f, 0.f, 0.f});
                 }
             }
+
+            // prefetch one tile ahead when the fragments of a tile are few registers
+            constexpr bool PF = NM1 * NA <= 12;
+            AT w1[NM1 ? NM1 : 1][NA];   // GEMM1 fragments of the current tile
+            AT w2[NM2 ? NM2 : 1][NA];   // GEMM2 fragments of the current tile
+            if constexpr (PF) {
+#pragma unroll
+                for (int m = 0; m < NM1; ++m) load_a<P, D>(w1[m], m1[m], 0, lane);
+            }
+
             Frag hb[NTC][NK];
 #pragma unroll
             for (int mt = 0; mt < NMT; ++mt) {
+                // prefetch: next GEMM1 tile, or the first GEMM2 tile after the last one
+                AT w1n[NM1 ? NM1 : 1][NA];
+                if constexpr (PF) {
+                    if (mt + 1 < NMT) {
+#pragma unroll
+                        for (int m = 0; m < NM1; ++m) load_a<P, D>(w1n[m], m1[m], mt + 1, lane);
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < NM2; ++m) load_a<P, D>(w2[m], m2[m], 0, lane);
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < NM1; ++m) load_a<P, D>(w1[m], m1[m], mt, lane);
+                }
+
                 // ---- projections z_pre, htilde for output units of tile mt
                 f32x4 az[NTC], ah[NTC];
-                if (l == 0) {
+                if constexpr (FIRST) {
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
                         const int o = st[c] * D + g * NS + 4 * mt;
                         az[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0z + o);
                         ah[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0h + o);
                     }
+                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah, w1[0], hv);
                 } else {
                     const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l] + g * NS + 4 * mt);
                     const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l] + g * NS + 4 * mt);
@@ -450,134 +581,121 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         az[c] = bz;
                         ah[c] = bh;
                     }
-                    mma_tile<P, D, NTC>(az, fz, mt, u, lane);
-                    mma_tile<P, D, NTC>(ah, fhu, mt, u, lane);
+                    mma_a<P, D, NTC>(az, w1[0], u);
+                    mma_a<P, D, NTC>(ah, w1[1], u);
+                    mma_a<P, D, NTC>(ah, w1[2], hv);
                 }
-                if (vert) mma_tile<P, D, NTC>(ah, fhv, mt, hv, lane);
 
                 // ---- gates and the chunked scan along the row
                 float h[NTC][4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float A[NTC], Bv[NTC];
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-                        const float z = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(az[c][i] * kNegLog2e));
-                        const float aa = z * keep[c];
-                        const float bb = fmaf(-z, ah[c][i], ah[c][i]);   // (1 - z) htilde
-                        if (c == 0) {
-                            A[c] = aa;
-                            Bv[c] = bb;
-                        } else {
-                            Bv[c] = fmaf(aa, Bv[c - 1], bb);
-                            A[c] = aa * A[c - 1];
-                        }
-                    }
-                    float al = 1.0f - A[NTC - 1], gb = Bv[NTC - 1];
-                    row_scan(al, gb);                   // chunks 0..lane of this DPP row
-                    float X = dpp0<0x111>(gb);          // carry entering this lane's chunk
-                    if constexpr (CROSS) {
-                        const float Xa = 1.0f - dpp0<0x111>(al);
-                        const int buf = (mt * 4 + i) & 1;
-                        if (r16 == 15) {
-                            xw[buf][wave][4 * g + i][0] = 1.0f - al;
-                            xw[buf][wave][4 * g + i][1] = gb;
-                        }
-                        __syncthreads();
-                        float W = 0.0f;
-                        for (int w = 0; w < wave; ++w) W = fmaf(xw[buf][w][4 * g + i][0], W, xw[buf][w][4 * g + i][1]);
-                        X = fmaf(Xa, W, X);
-                    }
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c) h[c][i] = fmaf(A[c], X, Bv[c]);
-                }
+                scan_tile<NTC, CROSS>(az, ah, keep, h, xw, mt, wave, g, r16);
 
-                // ---- outputs of tile mt: GEMM2 operand, frontier, residual
+                // ---- outputs of tile mt: GEMM2 operand, residual, chain head
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
                     set_pair<P, D>(hb[c], 4 * mt, h[c][0], h[c][1]);
                     set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
-                    if (!valid[c]) continue;
-                    if (keep_res) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
-                    if (G.chain) {   // head reads h directly
+                    if constexpr (KEEP_RES) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
+                    if constexpr (FIRST && !LAST) res[0][wave][c][mt][lane] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if constexpr (CHAIN) {   // head reads h directly
                         const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                        const f32x4 w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+                        const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             l0[c] = fmaf(w0[i], h[c][i], l0[c]);
-                            l1[c] = fmaf(w1[i], h[c][i], l1[c]);
+                            l1[c] = fmaf(w1h[i], h[c][i], l1[c]);
                         }
                     }
                 }
-            }
-            if (G.chain) break;
-
-            // h of this row is the next row's h_V: store whole 16-byte fragments
-            if (j + 1 < ly) {
+                if (PF && mt + 1 < NMT) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
-                    if (!valid[c]) continue;
-                    f32x4* dst = reinterpret_cast<f32x4*>(frow[c] + l * fl_stride);
+                    for (int m = 0; m < NM1; ++m)
 #pragma unroll
-                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
+                        for (int k = 0; k < NA; ++k) w1[m][k] = w1n[m][k];
                 }
             }
+            if constexpr (CHAIN) return;
+            else {
+                // h of this row is the next row's h_V: store whole 16-byte fragments
+                if (j + 1 < ly) {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        if (!valid[c]) continue;
+                        f32x4* dst = reinterpret_cast<f32x4*>(frow[c] + l * fl_stride);
+#pragma unroll
+                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
+                    }
+                }
 
-            // ---- x = GELU(C h + D u + s): accumulator seeded with the table (layer 0)
-            // or the residual row (layers >= 2); the last layer feeds the head directly
-            auto out_tile = [&](int mt, f32x4 (&ao)[NTC]) {
-                if (l == 0) {
+                // ---- x = GELU(C h + D u + s): the accumulator starts from the table (layer 0)
+                // or the residual row (zero for layer 1); the last layer feeds the head
+                Frag xn[NTC][LAST ? 1 : NK];
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c)
-                        ao[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
-                } else {
-                    if (l >= 2) {
+                for (int mt = 0; mt < NMT; ++mt) {
+                    AT w2n[NM2][NA];
+                    if constexpr (PF) {
+                        if (mt + 1 < NMT) {
 #pragma unroll
-                        for (int c = 0; c < NTC; ++c) ao[c] = res[(l - 1) & 1][wave][c][mt][lane];
+                            for (int m = 0; m < NM2; ++m) load_a<P, D>(w2n[m], m2[m], mt + 1, lane);
+                        }
                     } else {
 #pragma unroll
-                        for (int c = 0; c < NTC; ++c) ao[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                        for (int m = 0; m < NM2; ++m) load_a<P, D>(w2[m], m2[m], mt, lane);
                     }
-                    mma_tile<P, D, NTC>(ao, fd, mt, u, lane);
-                }
-                mma_tile<P, D, NTC>(ao, fc, mt, hb, lane);
-            };
-            if (!last) {
-                Frag xn[NTC][NK];
-#pragma unroll
-                for (int mt = 0; mt < NMT; ++mt) {
                     f32x4 ao[NTC];
-                    out_tile(mt, ao);
+                    if constexpr (FIRST) {
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-                        set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[c][0]), gelu_tail(ao[c][1]));
-                        set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[c][2]), gelu_tail(ao[c][3]));
+                        for (int c = 0; c < NTC; ++c)
+                            ao[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) ao[c] = res[(l - 1) & 1][wave][c][mt][lane];
+                        mma_a<P, D, NTC>(ao, w2[0], u);
                     }
-                }
+                    mma_a<P, D, NTC>(ao, w2[NM2 - 1], hb);
+                    if constexpr (!LAST) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c)
+                        for (int c = 0; c < NTC; ++c) {
+                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[c][0]), gelu_tail(ao[c][1]));
+                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[c][2]), gelu_tail(ao[c][3]));
+                        }
+                    } else {
+                        const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                        const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
 #pragma unroll
-                    for (int k = 0; k < NK; ++k) u[c][k] = xn[c][k];
-            } else {
+                        for (int c = 0; c < NTC; ++c) {
 #pragma unroll
-                for (int mt = 0; mt < NMT; ++mt) {
-                    f32x4 ao[NTC];
-                    out_tile(mt, ao);
-                    const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                    const f32x4 w1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const float x = gelu_tail(ao[c][i]);
-                            l0[c] = fmaf(w0[i], x, l0[c]);
-                            l1[c] = fmaf(w1[i], x, l1[c]);
+                            for (int i = 0; i < 4; ++i) {
+                                const float x = gelu_tail(ao[c][i]);
+                                l0[c] = fmaf(w0[i], x, l0[c]);
+                                l1[c] = fmaf(w1h[i], x, l1[c]);
+                            }
                         }
                     }
+                    if (PF && mt + 1 < NMT) {
+#pragma unroll
+                        for (int m = 0; m < NM2; ++m)
+#pragma unroll
+                            for (int k = 0; k < NA; ++k) w2[m][k] = w2n[m][k];
+                    }
+                }
+                if constexpr (!LAST) {
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) u[c][k] = xn[c][k];
                 }
             }
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if (CHAIN || nl == 1) {
+            layer(T_{}, T_{}, 0);
+        } else if constexpr (!CHAIN) {
+            layer(T_{}, F_{}, 0);
+            for (int l = 1; l + 1 < nl; ++l) layer(F_{}, F_{}, l);
+            layer(F_{}, T_{}, nl - 1);
         }
-
         // head: logits = W_o x + b_o, log p of the site's own spin
         const float bo0 = tab[a.pl.head_b], bo1 = tab[a.pl.head_b + 1];
 #pragma unroll
@@ -655,10 +773,18 @@ template <int P, int D, int NTC>
 static int launch_t(const FwdArgs& a, hipStream_t st) {
     const int64_t blocks = (a.q_count + a.sh.seqs - 1) / a.sh.seqs;
     if (blocks <= 0) return 0;
-    if (a.sh.cross_wave)
-        fwd_kernel<P, D, NTC, true><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
-    else
-        fwd_kernel<P, D, NTC, false><<<dim3((unsigned)blocks), dim3(kWaves * 64), 0, st>>>(a);
+    const dim3 grid((unsigned)blocks), block(kWaves * 64);
+    if (a.g.chain) {
+        if (a.sh.cross_wave)
+            fwd_kernel<P, D, NTC, true, true><<<grid, block, 0, st>>>(a);
+        else
+            fwd_kernel<P, D, NTC, false, true><<<grid, block, 0, st>>>(a);
+    } else {
+        if (a.sh.cross_wave)
+            fwd_kernel<P, D, NTC, true, false><<<grid, block, 0, st>>>(a);
+        else
+            fwd_kernel<P, D, NTC, false, false><<<grid, block, 0, st>>>(a);
+    }
     return (int)hipGetLastError();
 }
 
