@@ -224,9 +224,18 @@ __device__ inline void row_scan4(float (&A)[4], float (&B)[4]) {
     "v_mul_f32_dpp %5, %5, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
     "v_mul_f32_dpp %6, %6, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
     "v_mul_f32_dpp %7, %7, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
-    asm volatile("s_nop 1\n" PSR_SCAN_STEP("1") PSR_SCAN_STEP("2") PSR_SCAN_STEP("4") PSR_SCAN_STEP("8") "s_nop 1"
+    asm("s_nop 1\n" PSR_SCAN_STEP("1") PSR_SCAN_STEP("2") PSR_SCAN_STEP("4") PSR_SCAN_STEP("8") "s_nop 1"
                  : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
 #undef PSR_SCAN_STEP
+}
+
+// h = b + a * (B of lane - 1 in the DPP row), with the neighbour's register read
+// as the DPP source of the fmac; lane 0 of a row has no source and keeps b.
+// The DPP read of B follows its last write (in row_scan4) by at least the
+// trailing s_nop there.
+__device__ inline float carry_apply(float b, float a, float B) {
+    asm("v_fmac_f32_dpp %0, %1, %2 row_shr:1 row_mask:0xf bank_mask:0xf" : "+v"(b) : "v"(B), "v"(a));
+    return b;
 }
 
 // GELU(x) = x Phi(x) = max(x, 0) - |x| p(x) with the Gaussian tail
@@ -286,11 +295,12 @@ __device__ inline void mma_a(f32x4 (&acc)[NTC], const W& w, const B& b) {
 
 constexpr int kWaves = 4;
 constexpr float kNegLog2e = -1.4426950408889634f;
+constexpr float kLn2 = 0.69314718055994531f;
 
 // Gates and the chunked scan of one output tile (4 units per lane, NTC positions):
 //   z = sigmoid(az), a = z (0 at a row start), b = (1 - z) htilde,
 //   h = a h_prev + b along the row.
-template <int NTC, bool CROSS>
+template <int NTC, bool CROSS, bool ALIGNED>
 __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC], const float (&keep)[NTC],
                                  float (&h)[NTC][4], float (&xw)[2][kWaves][16][2], int mt, int wave, int g, int r16) {
     float A[NTC][4], Bv[NTC][4];   // maps of the positions, composed inside the chunk
@@ -299,7 +309,9 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
             const float z = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(az[c][i] * kNegLog2e));
-            const float aa = z * keep[c];
+            // ALIGNED: every row starts at position 0 of lane 0 of a DPP row, where the
+            // carry is zero and the multiplier is never applied, so a needs no mask
+            const float aa = ALIGNED ? z : z * keep[c];
             const float bb = fmaf(-z, ah[c][i], ah[c][i]);   // (1 - z) htilde
             if (c == 0) {
                 A[c][i] = aa;
@@ -317,10 +329,16 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
         sB[i] = Bv[NTC - 1][i];
     }
     row_scan4(sA, sB);
+    if constexpr (!CROSS) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < NTC; ++c) h[c][i] = carry_apply(Bv[c][i], A[c][i], sB[i]);
+    } else {
     float X[4];   // carry entering this lane's chunk
 #pragma unroll
     for (int i = 0; i < 4; ++i) X[i] = dpp0<0x111>(sB[i]);
-    if constexpr (CROSS) {
+    {
         const int buf = mt & 1;
         if (r16 == 15) {
 #pragma unroll
@@ -342,6 +360,7 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < NTC; ++c) h[c][i] = fmaf(A[c][i], X[i], Bv[c][i]);
+    }
 }
 
 // slots s, s+1 (s even) of a lane's operand array; BF16 packs the pair into one dword
@@ -402,7 +421,7 @@ __device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K]
 // also keeps sequences that share a chunk or a DPP row independent.
 
 
-template <int P, int D, int NTC, bool CROSS, bool CHAIN>
+template <int P, int D, int NTC, bool CROSS, bool CHAIN, bool ALIGNED>
 __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     using F = MF<P>;
     typedef typename F::Frag Frag;
@@ -496,15 +515,42 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 #pragma unroll
         for (int c = 0; c < NTC; ++c) l0[c] = l1[c] = 0.0f;
 
+        // h_V operand of the layer being computed: the previous row's frontier (0 on row 0).
+        // Layer 0's is loaded here; layer l+1's is loaded while layer l forms its output.
+        Frag hv[NTC][NK];
+        auto load_hv = [&](int l) {
+#pragma unroll
+            for (int c = 0; c < NTC; ++c) {
+                const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
+#pragma unroll
+                for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hv[c], k, src[k]);
+            }
+        };
+        if constexpr (!CHAIN) {
+            if (vert) {
+                load_hv(0);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k)
+                        frag_set16<P, D>(hv[c], k, f32x4{0.f, 0.f, 0.f, 0.f});
+            }
+        }
+
         // One layer.  FIRST: u is the one-hot layer-0 input (tables);  LAST: x feeds the head.
-        // Inside a layer there is no branch between the output tiles, and the weight
-        // fragments of the next tile are loaded while the current one is computed.
+        // Inside a layer there is no branch between the output tiles; the operands of
+        // the next tile (weight fragments, accumulator seeds) are loaded while the
+        // current one is computed.
         auto layer = [&](auto first_c, auto last_c, int l) {
             constexpr bool FIRST = decltype(first_c)::value;
             constexpr bool LAST = decltype(last_c)::value;
             constexpr bool KEEP_RES = !CHAIN && !FIRST && !LAST;   // h^(l) is the residual of layer l+1
             constexpr int NM1 = CHAIN ? 0 : (FIRST ? 1 : 3);       // GEMM1 matrices: (W_hV) or (W_z, W_hu, W_hV)
-            constexpr int NM2 = CHAIN ? 0 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
+            constexpr int NM2 = CHAIN ? 1 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
+            constexpr int NM1_ = NM1 ? NM1 : 1;
+            // prefetch one tile ahead when the fragments of a tile are few registers
+            constexpr bool PF = NM1 * NA <= 12;
             const uint8_t* m1[3];
             const uint8_t* m2[2];
             if constexpr (FIRST) {
@@ -518,69 +564,79 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 m2[1] = a.frag + a.pl.frag[l][4];
             }
 
-            Frag hv[NTC][NK];   // B operand: h_V of this layer (frontier of the previous row; 0 on row 0)
-            if constexpr (!CHAIN) {
-                if (vert) {
+            // GEMM1 operands of tile mt: fragments and the accumulator seeds
+            // (layer 0: table rows of the site's state; else the biases)
+            auto fetch1 = [&](int mt, AT (&w)[NM1_][NA], f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-                        const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
-#pragma unroll
-                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hv[c], k, src[k]);
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k)
-                            frag_set16<P, D>(hv[c], k, f32x4{0.f, 0.f, 0.f, 0.f});
-                }
-            }
-
-            // prefetch one tile ahead when the fragments of a tile are few registers
-            constexpr bool PF = NM1 * NA <= 12;
-            AT w1[NM1 ? NM1 : 1][NA];   // GEMM1 fragments of the current tile
-            AT w2[NM2 ? NM2 : 1][NA];   // GEMM2 fragments of the current tile
-            if constexpr (PF) {
-#pragma unroll
-                for (int m = 0; m < NM1; ++m) load_a<P, D>(w1[m], m1[m], 0, lane);
-            }
-
-            Frag hb[NTC][NK];
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                // prefetch: next GEMM1 tile, or the first GEMM2 tile after the last one
-                AT w1n[NM1 ? NM1 : 1][NA];
-                if constexpr (PF) {
-                    if (mt + 1 < NMT) {
-#pragma unroll
-                        for (int m = 0; m < NM1; ++m) load_a<P, D>(w1n[m], m1[m], mt + 1, lane);
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < NM2; ++m) load_a<P, D>(w2[m], m2[m], 0, lane);
-                    }
-                } else {
-#pragma unroll
-                    for (int m = 0; m < NM1; ++m) load_a<P, D>(w1[m], m1[m], mt, lane);
-                }
-
-                // ---- projections z_pre, htilde for output units of tile mt
-                f32x4 az[NTC], ah[NTC];
+                for (int m = 0; m < NM1; ++m) load_a<P, D>(w[m], m1[m], mt, lane);
                 if constexpr (FIRST) {
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
                         const int o = st[c] * D + g * NS + 4 * mt;
-                        az[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0z + o);
-                        ah[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0h + o);
+                        sz[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0z + o);
+                        sh[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0h + o);
                     }
-                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah, w1[0], hv);
                 } else {
                     const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l] + g * NS + 4 * mt);
                     const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l] + g * NS + 4 * mt);
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
-                        az[c] = bz;
-                        ah[c] = bh;
+                        sz[c] = bz;
+                        sh[c] = bh;
                     }
+                }
+            };
+            // GEMM2 operands of tile mt: fragments, the seed (layer 0: table row of D u;
+            // else the residual row, zero for layer 1) and the head rows (last layer)
+            auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC], f32x4& hw0, f32x4& hw1) {
+                if constexpr (!CHAIN) {
+#pragma unroll
+                    for (int m = 0; m < NM2; ++m) load_a<P, D>(w[m], m2[m], mt, lane);
+                    if constexpr (FIRST) {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c)
+                            so[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) so[c] = res[(l - 1) & 1][wave][c][mt][lane];
+                    }
+                }
+                if constexpr (LAST) {
+                    hw0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                    hw1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+                }
+            };
+
+            AT w1[NM1_][NA];
+            f32x4 s1z[NTC], s1h[NTC];
+            AT w2[NM2][NA];
+            f32x4 s2[NTC], hw0, hw1;
+            if constexpr (PF) fetch1(0, w1, s1z, s1h);
+
+            Frag hb[NTC][NK];
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                AT w1n[NM1_][NA];
+                f32x4 s1zn[NTC], s1hn[NTC];
+                if constexpr (PF) {
+                    if (mt + 1 < NMT)
+                        fetch1(mt + 1, w1n, s1zn, s1hn);
+                    else
+                        fetch2(0, w2, s2, hw0, hw1);
+                } else {
+                    fetch1(mt, w1, s1z, s1h);
+                }
+
+                // ---- projections z_pre, htilde for output units of tile mt
+                f32x4 az[NTC], ah[NTC];
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) {
+                    az[c] = s1z[c];
+                    ah[c] = s1h[c];
+                }
+                if constexpr (FIRST) {
+                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah, w1[0], hv);
+                } else {
                     mma_a<P, D, NTC>(az, w1[0], u);
                     mma_a<P, D, NTC>(ah, w1[1], u);
                     mma_a<P, D, NTC>(ah, w1[2], hv);
@@ -588,7 +644,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
                 // ---- gates and the chunked scan along the row
                 float h[NTC][4];
-                scan_tile<NTC, CROSS>(az, ah, keep, h, xw, mt, wave, g, r16);
+                scan_tile<NTC, CROSS, ALIGNED>(az, ah, keep, h, xw, mt, wave, g, r16);
 
                 // ---- outputs of tile mt: GEMM2 operand, residual, chain head
 #pragma unroll
@@ -612,6 +668,11 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     for (int m = 0; m < NM1; ++m)
 #pragma unroll
                         for (int k = 0; k < NA; ++k) w1[m][k] = w1n[m][k];
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        s1z[c] = s1zn[c];
+                        s1h[c] = s1hn[c];
+                    }
                 }
             }
             if constexpr (CHAIN) return;
@@ -626,32 +687,26 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
                     }
                 }
+                // the next layer's h_V, in flight during this layer's output
+                if constexpr (!LAST) {
+                    if (vert) load_hv(l + 1);
+                }
 
-                // ---- x = GELU(C h + D u + s): the accumulator starts from the table (layer 0)
-                // or the residual row (zero for layer 1); the last layer feeds the head
+                // ---- x = GELU(C h + D u + s); the last layer feeds the head
                 Frag xn[NTC][LAST ? 1 : NK];
 #pragma unroll
                 for (int mt = 0; mt < NMT; ++mt) {
                     AT w2n[NM2][NA];
+                    f32x4 s2n[NTC], hw0n, hw1n;
                     if constexpr (PF) {
-                        if (mt + 1 < NMT) {
-#pragma unroll
-                            for (int m = 0; m < NM2; ++m) load_a<P, D>(w2n[m], m2[m], mt + 1, lane);
-                        }
+                        if (mt + 1 < NMT) fetch2(mt + 1, w2n, s2n, hw0n, hw1n);
                     } else {
-#pragma unroll
-                        for (int m = 0; m < NM2; ++m) load_a<P, D>(w2[m], m2[m], mt, lane);
+                        fetch2(mt, w2, s2, hw0, hw1);
                     }
                     f32x4 ao[NTC];
-                    if constexpr (FIRST) {
 #pragma unroll
-                        for (int c = 0; c < NTC; ++c)
-                            ao[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < NTC; ++c) ao[c] = res[(l - 1) & 1][wave][c][mt][lane];
-                        mma_a<P, D, NTC>(ao, w2[0], u);
-                    }
+                    for (int c = 0; c < NTC; ++c) ao[c] = s2[c];
+                    if constexpr (!FIRST) mma_a<P, D, NTC>(ao, w2[0], u);
                     mma_a<P, D, NTC>(ao, w2[NM2 - 1], hb);
                     if constexpr (!LAST) {
 #pragma unroll
@@ -660,15 +715,13 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                             set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[c][2]), gelu_tail(ao[c][3]));
                         }
                     } else {
-                        const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                        const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const float x = gelu_tail(ao[c][i]);
-                                l0[c] = fmaf(w0[i], x, l0[c]);
-                                l1[c] = fmaf(w1h[i], x, l1[c]);
+                                l0[c] = fmaf(hw0[i], x, l0[c]);
+                                l1[c] = fmaf(hw1[i], x, l1[c]);
                             }
                         }
                     }
@@ -677,6 +730,10 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         for (int m = 0; m < NM2; ++m)
 #pragma unroll
                             for (int k = 0; k < NA; ++k) w2[m][k] = w2n[m][k];
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) s2[c] = s2n[c];
+                        hw0 = hw0n;
+                        hw1 = hw1n;
                     }
                 }
                 if constexpr (!LAST) {
@@ -708,7 +765,10 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             v0 += bo0;
             v1 += bo1;
             const float dl = own[c] ? (v0 - v1) : (v1 - v0);
-            const float lp = -(fmaxf(dl, 0.0f) + log1pf(__expf(-fabsf(dl))));
+            // log p = -softplus(dl) = -(max(dl, 0) + ln(1 + e^-|dl|)), in base 2 on the
+            // hardware exp2/log2 (1 + e rounds to 1 only where e < 2^-24)
+            const float e = __builtin_amdgcn_exp2f(fabsf(dl) * kNegLog2e);
+            const float lp = -(fmaxf(dl, 0.0f) + kLn2 * __builtin_amdgcn_logf(1.0f + e));
             if (valid[c]) {
                 neumaier(ls[c], lc[c], lp);
                 if (a.logp_site && g == 0) a.logp_site[(size_t)(q0 + kq[c]) * N + j * lx + iph[c]] = lp;
@@ -776,14 +836,15 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
     const dim3 grid((unsigned)blocks), block(kWaves * 64);
     if (a.g.chain) {
         if (a.sh.cross_wave)
-            fwd_kernel<P, D, NTC, true, true><<<grid, block, 0, st>>>(a);
+            fwd_kernel<P, D, NTC, true, true, false><<<grid, block, 0, st>>>(a);
         else
-            fwd_kernel<P, D, NTC, false, true><<<grid, block, 0, st>>>(a);
+            fwd_kernel<P, D, NTC, false, true, false><<<grid, block, 0, st>>>(a);
+    } else if (a.sh.cross_wave) {
+        fwd_kernel<P, D, NTC, true, false, false><<<grid, block, 0, st>>>(a);
+    } else if (a.g.lx == 16 * NTC) {
+        fwd_kernel<P, D, NTC, false, false, true><<<grid, block, 0, st>>>(a);
     } else {
-        if (a.sh.cross_wave)
-            fwd_kernel<P, D, NTC, true, false><<<grid, block, 0, st>>>(a);
-        else
-            fwd_kernel<P, D, NTC, false, false><<<grid, block, 0, st>>>(a);
+        fwd_kernel<P, D, NTC, false, false, false><<<grid, block, 0, st>>>(a);
     }
     return (int)hipGetLastError();
 }
