@@ -39,6 +39,12 @@ WORKLOADS = {
     "heisenberg10x10": dict(L=10, nl=2, d=64, B=4096, B_fp32=1024, k=1),
 }
 
+# HBM traffic of the forward kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by the same counters on a plain device copy of known size; valid only
+# for the kernel source it was measured on (its SHA-256 is recorded with it).
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fwd_kernel_heisenberg32x32_traffic.md")
+FWD_SOURCE = os.path.join(ROOT, "paper_2605_13807_amd", "csrc", "psr_fwd.hip")
+
 PEAK = {  # MI355X datasheet peaks (dense)
     "bf16_tflops": 2500.0,
     "fp32_tflops": 157.3,
@@ -49,6 +55,43 @@ PEAK = {  # MI355X datasheet peaks (dense)
 def flops_per_site(nl: int, d: int) -> float:
     """Algorithmic MFMA flops of one site-eval forward: 2 * (2 d^2 + 5 d^2 (nl-1) + 2 d)."""
     return 2.0 * (2 * d * d + 5 * d * d * (nl - 1) + 2 * d)
+
+
+def fwd_source_sha() -> str:
+    import hashlib
+    with open(FWD_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic() -> dict | None:
+    """Traffic per forward launch from the committed record, if it matches this kernel source."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = {}
+    with open(TRAFFIC_RECORD) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != fwd_source_sha():
+        return None
+    return {"bytes_per_launch": float(rec["hbm_bytes_per_launch"]),
+            "fetch_bytes_per_launch": float(rec["fetch_bytes_per_launch"]),
+            "write_bytes_per_launch": float(rec["write_bytes_per_launch"]),
+            "sequences_per_launch": int(rec["sequences_per_launch"])}
+
+
+def copy_calibration() -> int:
+    """A plain 1 GiB device-to-device copy: the reference that FETCH_SIZE / WRITE_SIZE are scaled by."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}))
+    return 0
 
 
 def main() -> int:
@@ -62,11 +105,15 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--chunk", type=int, default=32768)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference for the HBM traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: the hot path has no cross-GPU step "
-                                   "(samples shard with zero communication; see DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: samples shard across GPUs with no "
+                                   "communication in the hot path, which a single GPU cannot exercise",
                           "n_gpus": args.gpus}))
         return 2
 
@@ -142,11 +189,18 @@ def main() -> int:
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": None,
+        "traffic_note": "HBM bytes per forward launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated); "
+                        "null when the kernel source differs from the one profiled",
         "launches": r["fwd_launches"],
         "avg_launch_ms": round(r["fwd_ms"] / max(1, r["fwd_launches"]), 4),
         "flops_per_site_eval": F,
         "fwd_share_of_step": round(fwd_s / r["dt"], 4),
     }
+
+    tr = recorded_traffic()
+    if tr is not None:
+        roofline["traffic"] = tr["bytes_per_launch"]
+        roofline["traffic_sequences_per_launch"] = tr["sequences_per_launch"]
 
     # FP32 path on the same model (smaller batch; rate per site-eval)
     fp32 = None

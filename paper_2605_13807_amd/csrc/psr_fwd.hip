@@ -377,6 +377,19 @@ __device__ inline void set_pair(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, 
     }
 }
 
+// Keep the values of output tile mt (slots 4mt..4mt+3 of an operand array) at
+// this point of the program: an empty volatile asm that reads them stops the
+// compiler from sinking their computation into a later pipeline stage.
+template <int P, int D>
+__device__ inline void pin_tile(typename MF<P>::Frag (&f)[D / MF<P>::K], int mt) {
+    if constexpr (P == kBF16) {
+        asm volatile("" ::"v"(f[mt >> 1][2 * (mt & 1)]), "v"(f[mt >> 1][2 * (mt & 1) + 1]));
+    } else {
+        asm volatile("" ::"v"(f[4 * mt]), "v"(f[4 * mt + 1]), "v"(f[4 * mt + 2]), "v"(f[4 * mt + 3]));
+    }
+}
+__device__ inline void pin2(float& x, float& y) { asm volatile("" : "+v"(x), "+v"(y)); }
+
 // Row frontier (h of the previous row, the operand type of the projections):
 // per sequence-local index qi, layer l, physical column i, lane group g, the
 // lane's d/4 slots are contiguous, so a lane moves whole 16-byte fragments.
@@ -588,7 +601,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             };
             // GEMM2 operands of tile mt: fragments, the seed (layer 0: table row of D u;
             // else the residual row, zero for layer 1) and the head rows (last layer)
-            auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC], f32x4& hw0, f32x4& hw1) {
+            auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC]) {
                 if constexpr (!CHAIN) {
 #pragma unroll
                     for (int m = 0; m < NM2; ++m) load_a<P, D>(w[m], m2[m], mt, lane);
@@ -601,56 +614,44 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         for (int c = 0; c < NTC; ++c) so[c] = res[(l - 1) & 1][wave][c][mt][lane];
                     }
                 }
-                if constexpr (LAST) {
-                    hw0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                    hw1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
-                }
             };
 
-            AT w1[NM1_][NA];
-            f32x4 s1z[NTC], s1h[NTC];
-            AT w2[NM2][NA];
-            f32x4 s2[NTC], hw0, hw1;
-            if constexpr (PF) fetch1(0, w1, s1z, s1h);
+            // Two operand slots per phase.  With PF the phases are software-pipelined:
+            // iteration mt issues the MFMAs of tile mt+1, loads the operands of tile
+            // mt+2 and then runs the VALU epilogue of tile mt, so that the matrix core
+            // works while the VALU forms the previous tile's outputs.
+            constexpr int NSL = PF ? 2 : 1;
+            AT w1[NSL][NM1_][NA];
+            f32x4 s1z[NSL][NTC], s1h[NSL][NTC];
+            AT w2[NSL][NM2][NA];
+            f32x4 s2[NSL][NTC];
+            f32x4 az[NSL][NTC], ah[NSL][NTC], ao[NSL][NTC];
 
-            Frag hb[NTC][NK];
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                AT w1n[NM1_][NA];
-                f32x4 s1zn[NTC], s1hn[NTC];
-                if constexpr (PF) {
-                    if (mt + 1 < NMT)
-                        fetch1(mt + 1, w1n, s1zn, s1hn);
-                    else
-                        fetch2(0, w2, s2, hw0, hw1);
-                } else {
-                    fetch1(mt, w1, s1z, s1h);
-                }
-
-                // ---- projections z_pre, htilde for output units of tile mt
-                f32x4 az[NTC], ah[NTC];
+            auto issue1 = [&](int sl) {
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
-                    az[c] = s1z[c];
-                    ah[c] = s1h[c];
+                    az[sl][c] = s1z[sl][c];
+                    ah[sl][c] = s1h[sl][c];
                 }
                 if constexpr (FIRST) {
-                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah, w1[0], hv);
+                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah[sl], w1[sl][0], hv);
                 } else {
-                    mma_a<P, D, NTC>(az, w1[0], u);
-                    mma_a<P, D, NTC>(ah, w1[1], u);
-                    mma_a<P, D, NTC>(ah, w1[2], hv);
+                    mma_a<P, D, NTC>(az[sl], w1[sl][0], u);
+                    mma_a<P, D, NTC>(ah[sl], w1[sl][1], u);
+                    mma_a<P, D, NTC>(ah[sl], w1[sl][2], hv);
                 }
-
+            };
+            Frag hb[NTC][NK];
+            auto valu1 = [&](int mt, int sl) {
                 // ---- gates and the chunked scan along the row
                 float h[NTC][4];
-                scan_tile<NTC, CROSS, ALIGNED>(az, ah, keep, h, xw, mt, wave, g, r16);
-
+                scan_tile<NTC, CROSS, ALIGNED>(az[sl], ah[sl], keep, h, xw, mt, wave, g, r16);
                 // ---- outputs of tile mt: GEMM2 operand, residual, chain head
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
                     set_pair<P, D>(hb[c], 4 * mt, h[c][0], h[c][1]);
                     set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
+                    if constexpr (PF) pin_tile<P, D>(hb[c], mt);
                     if constexpr (KEEP_RES) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
                     if constexpr (FIRST && !LAST) res[0][wave][c][mt][lane] = f32x4{0.f, 0.f, 0.f, 0.f};
                     if constexpr (CHAIN) {   // head reads h directly
@@ -663,16 +664,28 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         }
                     }
                 }
-                if (PF && mt + 1 < NMT) {
+            };
+
+            if constexpr (PF) {
+                fetch1(0, w1[0], s1z[0], s1h[0]);
+                fetch1(1, w1[NSL - 1], s1z[NSL - 1], s1h[NSL - 1]);
+                issue1(0);
+            }
 #pragma unroll
-                    for (int m = 0; m < NM1; ++m)
-#pragma unroll
-                        for (int k = 0; k < NA; ++k) w1[m][k] = w1n[m][k];
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-                        s1z[c] = s1zn[c];
-                        s1h[c] = s1hn[c];
-                    }
+            for (int mt = 0; mt < NMT; ++mt) {
+                if constexpr (PF) {
+                    const int cs = mt & 1, ns = cs ^ 1;
+                    if (mt + 1 < NMT) issue1(ns);
+                    if (mt + 2 < NMT)
+                        fetch1(mt + 2, w1[cs], s1z[cs], s1h[cs]);
+                    else if constexpr (!CHAIN)
+                        fetch2(mt + 2 - NMT, w2[cs], s2[cs]);
+                    valu1(mt, cs);
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+                    fetch1(mt, w1[0], s1z[0], s1h[0]);
+                    issue1(0);
+                    valu1(mt, 0);
                 }
             }
             if constexpr (CHAIN) return;
@@ -694,46 +707,48 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
                 // ---- x = GELU(C h + D u + s); the last layer feeds the head
                 Frag xn[NTC][LAST ? 1 : NK];
+                auto issue2 = [&](int sl) {
 #pragma unroll
-                for (int mt = 0; mt < NMT; ++mt) {
-                    AT w2n[NM2][NA];
-                    f32x4 s2n[NTC], hw0n, hw1n;
-                    if constexpr (PF) {
-                        if (mt + 1 < NMT) fetch2(mt + 1, w2n, s2n, hw0n, hw1n);
-                    } else {
-                        fetch2(mt, w2, s2, hw0, hw1);
-                    }
-                    f32x4 ao[NTC];
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c) ao[c] = s2[c];
-                    if constexpr (!FIRST) mma_a<P, D, NTC>(ao, w2[0], u);
-                    mma_a<P, D, NTC>(ao, w2[NM2 - 1], hb);
+                    for (int c = 0; c < NTC; ++c) ao[sl][c] = s2[sl][c];
+                    if constexpr (!FIRST) mma_a<P, D, NTC>(ao[sl], w2[sl][0], u);
+                    mma_a<P, D, NTC>(ao[sl], w2[sl][NM2 - 1], hb);
+                };
+                auto valu2 = [&](int mt, int sl) {
                     if constexpr (!LAST) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
-                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[c][0]), gelu_tail(ao[c][1]));
-                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[c][2]), gelu_tail(ao[c][3]));
+                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[sl][c][0]), gelu_tail(ao[sl][c][1]));
+                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[sl][c][2]), gelu_tail(ao[sl][c][3]));
+                            if constexpr (PF) pin_tile<P, D>(xn[c], mt);
                         }
                     } else {
+                        const f32x4 hw0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
+                        const f32x4 hw1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                const float x = gelu_tail(ao[c][i]);
+                                const float x = gelu_tail(ao[sl][c][i]);
                                 l0[c] = fmaf(hw0[i], x, l0[c]);
                                 l1[c] = fmaf(hw1[i], x, l1[c]);
                             }
+                            if constexpr (PF) pin2(l0[c], l1[c]);
                         }
                     }
-                    if (PF && mt + 1 < NMT) {
+                };
+                if constexpr (PF) issue2(0);
 #pragma unroll
-                        for (int m = 0; m < NM2; ++m)
-#pragma unroll
-                            for (int k = 0; k < NA; ++k) w2[m][k] = w2n[m][k];
-#pragma unroll
-                        for (int c = 0; c < NTC; ++c) s2[c] = s2n[c];
-                        hw0 = hw0n;
-                        hw1 = hw1n;
+                for (int mt = 0; mt < NMT; ++mt) {
+                    if constexpr (PF) {
+                        const int cs = mt & 1, ns = cs ^ 1;
+                        if (mt + 1 < NMT) issue2(ns);
+                        if (mt + 2 < NMT) fetch2(mt + 2, w2[cs], s2[cs]);
+                        valu2(mt, cs);
+                        __builtin_amdgcn_sched_barrier(0);
+                    } else {
+                        fetch2(mt, w2[0], s2[0]);
+                        issue2(0);
+                        valu2(mt, 0);
                     }
                 }
                 if constexpr (!LAST) {
