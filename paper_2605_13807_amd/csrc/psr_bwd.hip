@@ -85,6 +85,60 @@ __device__ inline float u0_val(const Geom& G, const uint32_t* w, int j, int i, i
     return (j > 0 && spin_at(w, (j - 1) * G.lx + i) == k - 2) ? 1.0f : 0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// Dense products on the matrix cores (FP32 MFMA 16x16x4), operands in memory
+// ---------------------------------------------------------------------------
+//
+// C(m, n) (+)= sum_k A(m, k) B(k, n) with element (m, k) of A at a.p[m*a.sm + k*a.sk],
+// (k, n) of B at b.p[k*b.sk + n*b.sn] and (m, n) of C at c.p[m*c.sm + n*c.sn].
+// M is a multiple of 16; N and K are masked.  The workgroup's waves take the
+// 16x16 output tiles in turn; a lane holds rows 4*(lane/16)..+3 of column
+// lane%16 of a tile.  Must be called by the whole workgroup (no barrier inside).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+struct MA { const float* p; int64_t sm, sk; };
+struct MB { const float* p; int64_t sk, sn; };
+struct MC { float* p; int64_t sm, sn; };
+
+__device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int tm = M >> 4, tn = (N + 15) >> 4;
+    const int kq = lane >> 4, r16 = lane & 15;
+    for (int t = wave; t < tm * tn; t += nw) {
+        const int m0 = (t % tm) << 4, n0 = (t / tm) << 4;
+        const int n = n0 + r16;
+        const bool nok = n < N;
+        const float* ap = a.p + (int64_t)(m0 + r16) * a.sm;
+        const float* bp = b.p + (int64_t)(nok ? n : 0) * b.sn;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        // K in blocks of 32: the block's 16 loads are issued together, then 8 MFMAs
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            float av[8], bv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = k0 + 4 * q + kq;
+                const bool kok = k < K;
+                av[q] = kok ? ap[(int64_t)k * a.sk] : 0.0f;
+                bv[q] = (kok && nok) ? bp[(int64_t)k * b.sk] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc, 0, 0, 0);
+        }
+        if (nok) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float* cp = c.p + (int64_t)(m0 + 4 * kq + i) * c.sm + (int64_t)n * c.sn;
+                *cp = acc_in ? *cp + acc[i] : acc[i];
+            }
+        }
+    }
+}
+
+// Offset of the (chunk row r, layer l) slab of a chunk tensor: layer-major, so
+// that the rows of one layer are contiguous ([l][r][column][unit]).
+__device__ inline int64_t cidx(const BwdArgs& a, int r, int l) {
+    return ((int64_t)l * a.R + r) * a.g.lx * a.g.d;
+}
+
 // One row forward for every layer.  When `r >= 0` the row's intermediates
 // are stored in chunk slot r.  Updates the frontier and returns the row's
 // sum of log p (thread 0 only; others return 0).
@@ -95,34 +149,42 @@ __device__ float row_forward(const BwdArgs& a, const Buf& b, const uint32_t* w, 
     const int64_t F1 = (int64_t)lx * d;
     float logp_sum = 0.0f;
     float* X = b.ROWIN;            // [lx][d] current layer input x^(l) (layers >= 1)
-    float* Hrow = b.LAM;           // [lx][d] scratch for h of this layer (row)
+    float* Hrow = b.LAM;           // [lx][d] h of this layer (row)
+    const float* th = a.theta;
     for (int l = 0; l < nl; ++l) {
         const int du = G.chain ? 2 : (l == 0 ? 4 : d);
         const int64_t oWz = a.off[6 * l + 0], obz = a.off[6 * l + 1], oWh = a.off[6 * l + 2], obh = a.off[6 * l + 3];
-        const float* th = a.theta;
-        float* Zs = (r >= 0) ? b.Z + (r * nl + l) * F1 : b.GX;    // GX is free during the forward
-        float* HTs = (r >= 0) ? b.HT + (r * nl + l) * F1 : b.GRES;
+        float* Zs = (r >= 0) ? b.Z + cidx(a, r, l) : b.GX;       // GX is free during the forward
+        float* HTs = (r >= 0) ? b.HT + cidx(a, r, l) : b.GRES;
         const float* hv = b.front + l * F1;
         const bool vert = !G.chain && j > 0;
         const int ldh = G.chain ? du : du + d;   // row stride of W_h ([d][2] on the chain)
-        // projections z_pre, htilde
+        // projections: biases and the one-hot layer-0 input here, dense parts on MFMA
         for (int e = tid; e < lx * d; e += T) {
             const int i = e / d, m = e - i * d;
             float zp = th[obz + m], hp = th[obh + m];
-            for (int k = 0; k < du; ++k) {
-                const float uk = (l == 0) ? u0_val(G, w, j, i, k) : X[i * d + k];
-                zp = fmaf(th[oWz + (int64_t)m * du + k], uk, zp);
-                hp = fmaf(th[oWh + (int64_t)m * ldh + k], uk, hp);
+            if (l == 0) {
+                for (int k = 0; k < du; ++k) {
+                    const float uk = u0_val(G, w, j, i, k);
+                    zp = fmaf(th[oWz + (int64_t)m * du + k], uk, zp);
+                    hp = fmaf(th[oWh + (int64_t)m * ldh + k], uk, hp);
+                }
             }
-            if (vert)
-                for (int k = 0; k < d; ++k) hp = fmaf(th[oWh + (int64_t)m * ldh + du + k], hv[i * d + k], hp);
-            Zs[i * d + m] = sigm(zp);
-            HTs[i * d + m] = hp;
+            Zs[e] = zp;
+            HTs[e] = hp;
             if (r >= 0) {
-                b.HV[(r * nl + l) * F1 + i * d + m] = vert ? hv[i * d + m] : 0.0f;
-                if (l > 0) b.XIN[(r * nl + l) * F1 + i * d + m] = X[i * d + m];
+                b.HV[cidx(a, r, l) + e] = vert ? hv[e] : 0.0f;
+                if (l > 0) b.XIN[cidx(a, r, l) + e] = X[e];
             }
         }
+        __syncthreads();
+        if (l >= 1) {
+            gemm(d, lx, d, MA{th + oWz, du, 1}, MB{X, 1, d}, MC{Zs, 1, d}, true);
+            gemm(d, lx, d, MA{th + oWh, ldh, 1}, MB{X, 1, d}, MC{HTs, 1, d}, true);
+        }
+        if (vert) gemm(d, lx, d, MA{th + oWh + du, ldh, 1}, MB{hv, 1, d}, MC{HTs, 1, d}, true);
+        __syncthreads();
+        for (int e = tid; e < lx * d; e += T) Zs[e] = sigm(Zs[e]);
         __syncthreads();
         // sequential recurrence along the snake row, one thread per unit
         for (int m = tid; m < d; m += T) {
@@ -136,9 +198,9 @@ __device__ float row_forward(const BwdArgs& a, const Buf& b, const uint32_t* w, 
         }
         __syncthreads();
         if (G.chain) {
-            // head directly on h (stored as PRE-less chain: keep h in H)
+            // the head reads h directly
             for (int e = tid; e < lx * d; e += T) {
-                if (r >= 0) b.H[(r * nl + l) * F1 + e] = Hrow[e];
+                if (r >= 0) b.H[cidx(a, r, l) + e] = Hrow[e];
                 X[e] = Hrow[e];
             }
             __syncthreads();
@@ -146,22 +208,22 @@ __device__ float row_forward(const BwdArgs& a, const Buf& b, const uint32_t* w, 
         }
         // output x = GELU(C h + D u + s)
         const int64_t oC = a.off[6 * l + 4], oD = a.off[6 * l + 5];
-        float* Ps = (r >= 0) ? b.PRE + (r * nl + l) * F1 : b.GZP;   // GZP free during the forward
+        float* Ps = (r >= 0) ? b.PRE + cidx(a, r, l) : b.GZP;   // GZP free during the forward
         for (int e = tid; e < lx * d; e += T) {
             const int i = e / d, m = e - i * d;
             float p = 0.0f;
-            for (int k = 0; k < d; ++k) p = fmaf(th[oC + (int64_t)m * d + k], Hrow[i * d + k], p);
             if (l == 0) {
                 for (int k = 0; k < 4; ++k) p = fmaf(th[oD + (int64_t)m * 4 + k], u0_val(G, w, j, i, k), p);
-            } else {
-                for (int k = 0; k < d; ++k) p = fmaf(th[oD + (int64_t)m * d + k], X[i * d + k], p);
             }
-            if (l >= 2) p += b.front[(l - 1) * F1 + i * d + m];   // h^(l-1) of this row (frontier already updated)
-            Ps[i * d + m] = p;
+            if (l >= 2) p += b.front[(l - 1) * F1 + e];   // h^(l-1) of this row (frontier already updated)
+            Ps[e] = p;
         }
         __syncthreads();
+        gemm(d, lx, d, MA{th + oC, d, 1}, MB{Hrow, 1, d}, MC{Ps, 1, d}, true);
+        if (l >= 1) gemm(d, lx, d, MA{th + oD, d, 1}, MB{X, 1, d}, MC{Ps, 1, d}, true);
+        __syncthreads();
         for (int e = tid; e < lx * d; e += T) {
-            if (r >= 0) b.H[(r * nl + l) * F1 + e] = Hrow[e];
+            if (r >= 0) b.H[cidx(a, r, l) + e] = Hrow[e];
             b.front[l * F1 + e] = Hrow[e];
             X[e] = gelu(Ps[e]);
         }
@@ -202,6 +264,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
     Buf b = carve(a.scratch + s * a.per_sample, a.nch, a.R, nl, lx, d);
     const int64_t F = (int64_t)nl * lx * d, F1 = (int64_t)lx * d;
     float* Orow = a.O + s * a.P;
+    const float* th = a.theta;
 
     // ---- phase 0: forward with checkpoints -------------------------------
     for (int64_t e = tid; e < F; e += T) b.front[e] = 0.0f;
@@ -243,31 +306,31 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
             for (int e = tid; e < lx * d; e += T) {
                 const int i = e / d, m = e - i * d;
                 const float g0 = b.GLOG[(r * lx + i) * 2], g1 = b.GLOG[(r * lx + i) * 2 + 1];
-                b.GX[e] = a.theta[oWo + m] * g0 + a.theta[oWo + d + m] * g1;
+                b.GX[e] = th[oWo + m] * g0 + th[oWo + d + m] * g1;
             }
             for (int64_t e = tid; e < F; e += T) b.GRES[e] = 0.0f;
             __syncthreads();
             for (int l = nl - 1; l >= 0; --l) {
                 const int du = G.chain ? 2 : (l == 0 ? 4 : d);
-                const int64_t base = (int64_t)(r * nl + l) * F1;
+                const int ldh = G.chain ? du : du + d;
+                const int64_t base = cidx(a, r, l);
                 float* gpre = b.GPRE + base;
                 float* gzp = b.GZP + base;
                 float* ght = b.GHT + base;
                 const float* Z = b.Z + base;
                 const float* HT = b.HT + base;
                 const float* Hh = b.H + base;
-                // g_pre and the direct adjoint of h
+                // g_pre and the direct adjoint of h: lambda = g_h(row below) + g_res + C^T g_pre
                 if (!G.chain) {
                     const int64_t oC = a.off[6 * l + 4];
-                    for (int e = tid; e < lx * d; e += T) gpre[e] = b.GX[e] * gelu_d(b.PRE[base + e]);
-                    __syncthreads();
                     for (int e = tid; e < lx * d; e += T) {
-                        const int i = e / d, m = e - i * d;
-                        float gh = gin[l * F1 + e] + b.GRES[l * F1 + e];
-                        for (int k = 0; k < d; ++k) gh = fmaf(a.theta[oC + (int64_t)k * d + m], gpre[i * d + k], gh);
-                        b.LAM[e] = gh;
-                        if (l >= 2) b.GRES[(l - 1) * F1 + e] = gpre[e];
+                        const float gp = b.GX[e] * gelu_d(b.PRE[base + e]);
+                        gpre[e] = gp;
+                        b.LAM[e] = gin[l * F1 + e] + b.GRES[l * F1 + e];
+                        if (l >= 2) b.GRES[(l - 1) * F1 + e] = gp;
                     }
+                    __syncthreads();
+                    gemm(d, lx, d, MA{th + oC, 1, d}, MB{gpre, 1, d}, MC{b.LAM, 1, d}, true);
                 } else {
                     for (int e = tid; e < lx * d; e += T) b.LAM[e] = b.GX[e];
                 }
@@ -294,24 +357,12 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
                 // adjoints of the inputs: vertical (to row j-1) and, for l >= 1, the layer input
                 const int64_t oWz = a.off[6 * l + 0], oWh = a.off[6 * l + 2];
                 const bool vert = !G.chain && j > 0;
-                for (int e = tid; e < lx * d; e += T) {
-                    const int i = e / d, k = e - i * d;
-                    if (vert) {
-                        float gv = 0.0f;
-                        for (int m = 0; m < d; ++m)
-                            gv = fmaf(a.theta[oWh + (int64_t)m * (du + d) + du + k], ght[i * d + m], gv);
-                        gout[l * F1 + e] = gv;
-                    }
-                    if (l >= 1) {
-                        const int64_t oD = a.off[6 * l + 5];
-                        float gu = 0.0f;
-                        for (int m = 0; m < d; ++m) {
-                            gu = fmaf(a.theta[oWz + (int64_t)m * du + k], gzp[i * d + m], gu);
-                            gu = fmaf(a.theta[oWh + (int64_t)m * (du + d) + k], ght[i * d + m], gu);
-                            gu = fmaf(a.theta[oD + (int64_t)m * du + k], gpre[i * d + m], gu);
-                        }
-                        b.ROWIN[e] = gu;
-                    }
+                if (vert) gemm(d, lx, d, MA{th + oWh + du, 1, ldh}, MB{ght, 1, d}, MC{gout + l * F1, 1, d}, false);
+                if (l >= 1) {
+                    const int64_t oD = a.off[6 * l + 5];
+                    gemm(d, lx, d, MA{th + oWz, 1, du}, MB{gzp, 1, d}, MC{b.ROWIN, 1, d}, false);
+                    gemm(d, lx, d, MA{th + oWh, 1, ldh}, MB{ght, 1, d}, MC{b.ROWIN, 1, d}, true);
+                    gemm(d, lx, d, MA{th + oD, 1, du}, MB{gpre, 1, d}, MC{b.ROWIN, 1, d}, true);
                 }
                 __syncthreads();
                 if (l >= 1) {
@@ -323,70 +374,53 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
             __syncthreads();
         }
 
-        // weight gradients of this chunk, added to the sample's row of O
+        // weight gradients of this chunk, added to the sample's row of O:
+        // outer products summed over the chunk's sites (S of them, contiguous per layer)
         const int nrow = j1 - j0;
+        const int S = nrow * lx;
         for (int l = 0; l < nl; ++l) {
             const int du = G.chain ? 2 : (l == 0 ? 4 : d);
+            const int ldh = G.chain ? du : du + d;
             const int64_t oWz = a.off[6 * l + 0], obz = a.off[6 * l + 1], oWh = a.off[6 * l + 2],
                           obh = a.off[6 * l + 3];
-            // W_z, W_h (u part and h_V part), D: rows m, columns k
-            const int KW = du + d;
-            for (int e = tid; e < d * KW; e += T) {
-                const int m = e / KW, k = e - m * KW;
-                float gw = 0.0f, gz = 0.0f, gd = 0.0f;
-                for (int rr = 0; rr < nrow; ++rr) {
-                    const int jj = j0 + rr;
-                    const int64_t base = (int64_t)(rr * nl + l) * F1;
-                    for (int i = 0; i < lx; ++i) {
-                        float in;
-                        if (k < du) {
-                            if (l == 0) {
-                                in = u0_val(G, w, jj, i, k);
-                            } else {
-                                in = b.XIN[base + i * d + k];
-                            }
-                        } else {
-                            in = b.HV[base + i * d + (k - du)];
-                        }
-                        gw = fmaf(b.GHT[base + i * d + m], in, gw);
-                        if (k < du) {
-                            gz = fmaf(b.GZP[base + i * d + m], in, gz);
-                            if (!G.chain) gd = fmaf(b.GPRE[base + i * d + m], in, gd);
+            const int64_t L = cidx(a, 0, l);
+            if (l >= 1) {
+                // dW(m, k) = sum_s g(s, m) x(s, k), formed as its transpose so a lane's 4 results are contiguous
+                gemm(d, d, S, MA{b.XIN + L, 1, d}, MB{b.GZP + L, d, 1}, MC{Orow + oWz, 1, du}, true);
+                gemm(d, d, S, MA{b.XIN + L, 1, d}, MB{b.GHT + L, d, 1}, MC{Orow + oWh, 1, ldh}, true);
+                gemm(d, d, S, MA{b.XIN + L, 1, d}, MB{b.GPRE + L, d, 1}, MC{Orow + a.off[6 * l + 5], 1, du}, true);
+            } else {
+                // one-hot layer-0 input (chain: previous spin)
+                for (int e = tid; e < d * du; e += T) {
+                    const int m = e / du, k = e - m * du;
+                    float gw = 0.0f, gz = 0.0f, gd = 0.0f;
+                    for (int rr = 0; rr < nrow; ++rr) {
+                        const int64_t bs = cidx(a, rr, 0);
+                        for (int i = 0; i < lx; ++i) {
+                            if (u0_val(G, w, j0 + rr, i, k) == 0.0f) continue;
+                            gw += b.GHT[bs + i * d + m];
+                            gz += b.GZP[bs + i * d + m];
+                            if (!G.chain) gd += b.GPRE[bs + i * d + m];
                         }
                     }
-                }
-                if (G.chain && k >= du) continue;
-                Orow[oWh + (int64_t)m * (G.chain ? du : KW) + k] += gw;
-                if (k < du) {
+                    Orow[oWh + (int64_t)m * ldh + k] += gw;
                     Orow[oWz + (int64_t)m * du + k] += gz;
                     if (!G.chain) Orow[a.off[6 * l + 5] + (int64_t)m * du + k] += gd;
                 }
             }
+            if (!G.chain) {
+                gemm(d, d, S, MA{b.HV + L, 1, d}, MB{b.GHT + L, d, 1}, MC{Orow + oWh + du, 1, ldh}, true);
+                gemm(d, d, S, MA{b.H + L, 1, d}, MB{b.GPRE + L, d, 1}, MC{Orow + a.off[6 * l + 4], 1, d}, true);
+            }
             // biases
             for (int m = tid; m < d; m += T) {
                 float sz = 0.0f, sh = 0.0f;
-                for (int rr = 0; rr < nrow; ++rr) {
-                    const int64_t base = (int64_t)(rr * nl + l) * F1;
-                    for (int i = 0; i < lx; ++i) {
-                        sz += b.GZP[base + i * d + m];
-                        sh += b.GHT[base + i * d + m];
-                    }
+                for (int e = 0; e < S; ++e) {
+                    sz += b.GZP[L + (int64_t)e * d + m];
+                    sh += b.GHT[L + (int64_t)e * d + m];
                 }
                 Orow[obz + m] += sz;
                 Orow[obh + m] += sh;
-            }
-            // C
-            if (!G.chain) {
-                const int64_t oC = a.off[6 * l + 4];
-                for (int e = tid; e < d * d; e += T) {
-                    const int m = e / d, k = e - m * d;
-                    float gc = 0.0f;
-                    for (int rr = 0; rr < nrow; ++rr) {
-                        const int64_t base = (int64_t)(rr * nl + l) * F1;
-                        for (int i = 0; i < lx; ++i) gc = fmaf(b.GPRE[base + i * d + m], b.H[base + i * d + k], gc);
-                    }
-                    Orow[oC + e] += gc;
-                }
             }
             __syncthreads();
         }
@@ -394,12 +428,11 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
         for (int e = tid; e < 2 * d + 2; e += T) {
             float acc = 0.0f;
             for (int rr = 0; rr < nrow; ++rr) {
+                const int64_t bs = cidx(a, rr, nl - 1);
                 for (int i = 0; i < lx; ++i) {
                     if (e < 2 * d) {
                         const int k = e / d, m = e - k * d;
-                        float x;
-                        const int64_t base = (int64_t)(rr * nl + (nl - 1)) * F1;
-                        x = G.chain ? b.H[base + i * d + m] : gelu(b.PRE[base + i * d + m]);
+                        const float x = G.chain ? b.H[bs + i * d + m] : gelu(b.PRE[bs + i * d + m]);
                         acc = fmaf(b.GLOG[(rr * lx + i) * 2 + k], x, acc);
                     } else {
                         acc += b.GLOG[(rr * lx + i) * 2 + (e - 2 * d)];
