@@ -95,10 +95,13 @@ __device__ inline float u0_val(const Geom& G, const uint32_t* w, int j, int i, i
 // 16x16 output tiles in turn; a lane holds rows 4*(lane/16)..+3 of column
 // lane%16 of a tile.  Must be called by the whole workgroup (no barrier inside).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-struct MA { const float* p; int64_t sm, sk; };
-struct MB { const float* p; int64_t sk, sn; };
-struct MC { float* p; int64_t sm, sn; };
+struct MA { const float* p; int sm, sk; };
+struct MB { const float* p; int sk, sn; };
+struct MC { float* p; int sm, sn; };
 
+// Offsets are 32-bit element offsets from a workgroup-uniform base (every
+// operand lives in one sample's scratch, its row of O or theta), so the loads
+// take the scalar-base + 32-bit-offset form.
 __device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int tm = M >> 4, tn = (N + 15) >> 4;
@@ -107,8 +110,7 @@ __device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
         const int m0 = (t % tm) << 4, n0 = (t / tm) << 4;
         const int n = n0 + r16;
         const bool nok = n < N;
-        const float* ap = a.p + (int64_t)(m0 + r16) * a.sm;
-        const float* bp = b.p + (int64_t)(nok ? n : 0) * b.sn;
+        const int ao = (m0 + r16) * a.sm, bo = (nok ? n : 0) * b.sn;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         // K in blocks of 32: the block's 16 loads are issued together, then 8 MFMAs
         for (int k0 = 0; k0 < K; k0 += 32) {
@@ -117,8 +119,8 @@ __device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
             for (int q = 0; q < 8; ++q) {
                 const int k = k0 + 4 * q + kq;
                 const bool kok = k < K;
-                av[q] = kok ? ap[(int64_t)k * a.sk] : 0.0f;
-                bv[q] = (kok && nok) ? bp[(int64_t)k * b.sk] : 0.0f;
+                av[q] = kok ? a.p[ao + k * a.sk] : 0.0f;
+                bv[q] = (kok && nok) ? b.p[bo + k * b.sk] : 0.0f;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc, 0, 0, 0);
@@ -126,7 +128,7 @@ __device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
         if (nok) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float* cp = c.p + (int64_t)(m0 + 4 * kq + i) * c.sm + (int64_t)n * c.sn;
+                float* cp = c.p + ((m0 + 4 * kq + i) * c.sm + n * c.sn);
                 *cp = acc_in ? *cp + acc[i] : acc[i];
             }
         }
