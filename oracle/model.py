@@ -294,7 +294,7 @@ def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool, bf16: bool 
             h[:, cols] = hs
             xt = R(h) @ P[f"C{l}"].T + ui @ P[f"D{l}"].T
             if l >= 2:
-                xt = xt + h_below
+                xt = xt + R(h_below)
             u = gelu(xt)
             frontier[l] = h
             h_below = h
@@ -316,7 +316,9 @@ def forward(theta, spins, m: Model, mode: str = "seq", keep_hidden: bool = False
     ``bf16`` evaluates the reduced-precision reading of the model: the operands
     of the dense projections (weight matrices acting on d-dimensional
     activations, and those activations: x^(l>=1), h_V and h) are rounded to
-    bfloat16 (nearest, ties to even) and everything else is exact.  The chain
+    bfloat16 (nearest, ties to even), the residual s = h^(l-1) is added in its
+    bfloat16 rounding (the row's h is kept once, in bfloat16), and everything
+    else is exact.  The chain
     has no such projection, so the flag does not change it.
     """
     spins = np.asarray(spins)

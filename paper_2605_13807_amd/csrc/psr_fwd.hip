@@ -294,6 +294,8 @@ __device__ inline void mma_a(f32x4 (&acc)[NTC], const W& w, const B& b) {
 }
 
 constexpr int kWaves = 4;
+// LDS for a workgroup's BF16 row frontier (and one zero row)
+constexpr int kLdsFrontier = 112 * 1024;
 constexpr float kNegLog2e = -1.4426950408889634f;
 constexpr float kLn2 = 0.69314718055994531f;
 
@@ -434,7 +436,7 @@ __device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K]
 // also keeps sequences that share a chunk or a DPP row independent.
 
 
-template <int P, int D, int NTC, bool CROSS, bool CHAIN, bool ALIGNED>
+template <int P, int D, int NTC, bool CROSS, bool CHAIN, bool ALIGNED, bool LDSF>
 __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     using F = MF<P>;
     typedef typename F::Frag Frag;
@@ -447,9 +449,12 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
     __shared__ float xw[2][kWaves][16][2];
     __shared__ float red[COLS][2];
-    // residual rows h^(l) of layers l >= 1, double-buffered by layer parity:
-    // [parity][wave][tile][output tile][lane] x 4 floats (16 B per lane, conflict-free)
-    __shared__ f32x4 res[2][kWaves][NTC][NMT][64];
+    // LDSF: the row frontier lives in LDS, [seq][layer][column] rows of PITCH bytes
+    // (padded by 16 B so that the 16 columns of a DPP row hit distinct banks),
+    // after one zero row that stands in for the residual of layers 0 and 1
+    constexpr int PITCH = D * F::ELT + 16;
+    constexpr int ZOFF = D * F::ELT;
+    __shared__ __attribute__((aligned(16))) uint8_t fl[LDSF ? kLdsFrontier : 16];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
@@ -462,6 +467,9 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     if (a.q_total) q_end = min(q_end, *a.q_total);
     const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * seqs;
     if (q0 >= q_end) return;   // uniform across the workgroup
+    if constexpr (LDSF) {
+        for (int e = threadIdx.x; e < ZOFF / 4; e += blockDim.x) reinterpret_cast<uint32_t*>(fl)[e] = 0u;
+    }
 
     // per-column constants (column = chunk position c of this lane), kept in 32-bit fields
     int t[NTC], kq[NTC], srow[NTC], flip[NTC];
@@ -500,7 +508,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     for (int c = 0; c < NTC; ++c) ls[c] = lc[c] = 0.0f;
 
     Frag u[NTC][NK];    // B operand: input of the current layer (layers >= 1)
-    const size_t fl_stride = (size_t)lx * D * F::ELT;   // frontier bytes per layer
+    // frontier bytes per layer
+    const size_t fl_stride = LDSF ? (size_t)lx * PITCH : (size_t)lx * D * F::ELT;
 
     for (int j = 0; j < ly; ++j) {
         __syncthreads();   // frontier of row j-1 is complete
@@ -523,7 +532,12 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
         // this row's frontier columns (layer l adds l * fl_stride bytes)
         uint8_t* frow[NTC];
 #pragma unroll
-        for (int c = 0; c < NTC; ++c) frow[c] = col_ptr<F::ELT, D>(a.frontier, seq_local(c), 0, nl, lx, iph[c], g);
+        for (int c = 0; c < NTC; ++c) {
+            if constexpr (LDSF)
+                frow[c] = fl + ZOFF + ((size_t)((valid[c] ? kq[c] : 0) * nl) * lx + iph[c]) * PITCH + g * (D / 4) * F::ELT;
+            else
+                frow[c] = col_ptr<F::ELT, D>(a.frontier, seq_local(c), 0, nl, lx, iph[c], g);
+        }
         float l0[NTC], l1[NTC];   // head logits, accumulated over the last layer's output tiles
 #pragma unroll
         for (int c = 0; c < NTC; ++c) l0[c] = l1[c] = 0.0f;
@@ -558,7 +572,6 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
         auto layer = [&](auto first_c, auto last_c, int l) {
             constexpr bool FIRST = decltype(first_c)::value;
             constexpr bool LAST = decltype(last_c)::value;
-            constexpr bool KEEP_RES = !CHAIN && !FIRST && !LAST;   // h^(l) is the residual of layer l+1
             constexpr int NM1 = CHAIN ? 0 : (FIRST ? 1 : 3);       // GEMM1 matrices: (W_hV) or (W_z, W_hu, W_hV)
             constexpr int NM2 = CHAIN ? 1 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
             constexpr int NM1_ = NM1 ? NM1 : 1;
@@ -576,6 +589,20 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 m2[0] = a.frag + a.pl.frag[l][3];
                 m2[1] = a.frag + a.pl.frag[l][4];
             }
+
+            // source of the residual h^(l-1) (layers >= 2): this row's frontier of layer l-1;
+            // layers 0 and 1 read the zero row (LDS frontier) or scale by 0 (global frontier)
+            const uint8_t* rsrc[NTC];
+            float rs = 1.0f;
+#pragma unroll
+            for (int c = 0; c < NTC; ++c) {
+                if constexpr (LDSF)
+                    rsrc[c] = (l >= 2) ? frow[c] + (l - 1) * fl_stride : fl + g * (D / 4) * F::ELT;
+                else
+                    rsrc[c] = frow[c] + (l >= 1 ? l - 1 : 0) * fl_stride;
+            }
+            if constexpr (!LDSF) rs = (l >= 2) ? 1.0f : 0.0f;
+            (void)rs;
 
             // GEMM1 operands of tile mt: fragments and the accumulator seeds
             // (layer 0: table rows of the site's state; else the biases)
@@ -610,8 +637,17 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         for (int c = 0; c < NTC; ++c)
                             so[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
                     } else {
+                        // residual h^(l-1) of this row, from the frontier (layers >= 2)
 #pragma unroll
-                        for (int c = 0; c < NTC; ++c) so[c] = res[(l - 1) & 1][wave][c][mt][lane];
+                        for (int c = 0; c < NTC; ++c) {
+                            if constexpr (P == kBF16) {
+                                const uint2 v = *reinterpret_cast<const uint2*>(rsrc[c] + 8 * mt);
+                                so[c] = f32x4{__builtin_bit_cast(float, v.x << 16), __builtin_bit_cast(float, v.x & 0xFFFF0000u),
+                                              __builtin_bit_cast(float, v.y << 16), __builtin_bit_cast(float, v.y & 0xFFFF0000u)};
+                            } else {
+                                so[c] = *reinterpret_cast<const f32x4*>(rsrc[c] + 16 * mt) * rs;
+                            }
+                        }
                     }
                 }
             };
@@ -652,8 +688,6 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     set_pair<P, D>(hb[c], 4 * mt, h[c][0], h[c][1]);
                     set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
                     if constexpr (PF) pin_tile<P, D>(hb[c], mt);
-                    if constexpr (KEEP_RES) res[l & 1][wave][c][mt][lane] = f32x4{h[c][0], h[c][1], h[c][2], h[c][3]};
-                    if constexpr (FIRST && !LAST) res[0][wave][c][mt][lane] = f32x4{0.f, 0.f, 0.f, 0.f};
                     if constexpr (CHAIN) {   // head reads h directly
                         const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
                         const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
@@ -690,15 +724,13 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             }
             if constexpr (CHAIN) return;
             else {
-                // h of this row is the next row's h_V: store whole 16-byte fragments
-                if (j + 1 < ly) {
+                // h of this row: the next row's h_V and the residual of layer l+2
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c) {
-                        if (!valid[c]) continue;
-                        f32x4* dst = reinterpret_cast<f32x4*>(frow[c] + l * fl_stride);
+                for (int c = 0; c < NTC; ++c) {
+                    if (!valid[c]) continue;
+                    f32x4* dst = reinterpret_cast<f32x4*>(frow[c] + l * fl_stride);
 #pragma unroll
-                        for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
-                    }
+                    for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
                 }
                 // the next layer's h_V, in flight during this layer's output
                 if constexpr (!LAST) {
@@ -841,6 +873,9 @@ FwdShape fwd_shape(const Geom& g) {
         const int c0 = k * g.lx, c1 = (k + 1) * g.lx - 1;
         if (c0 / per_wave != c1 / per_wave) s.cross_wave = 1;
     }
+    const int64_t pitch = (int64_t)g.d * 2 + 16;
+    s.lds_frontier = (!g.chain && g.prec == kBF16 &&
+                      (int64_t)g.d * 2 + (int64_t)s.seqs * g.nl * g.lx * pitch <= kLdsFrontier) ? 1 : 0;
     return s;
 }
 
@@ -851,15 +886,25 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
     const dim3 grid((unsigned)blocks), block(kWaves * 64);
     if (a.g.chain) {
         if (a.sh.cross_wave)
-            fwd_kernel<P, D, NTC, true, true, false><<<grid, block, 0, st>>>(a);
+            fwd_kernel<P, D, NTC, true, true, false, false><<<grid, block, 0, st>>>(a);
         else
-            fwd_kernel<P, D, NTC, false, true, false><<<grid, block, 0, st>>>(a);
-    } else if (a.sh.cross_wave) {
-        fwd_kernel<P, D, NTC, true, false, false><<<grid, block, 0, st>>>(a);
-    } else if (a.g.lx == 16 * NTC) {
-        fwd_kernel<P, D, NTC, false, false, true><<<grid, block, 0, st>>>(a);
+            fwd_kernel<P, D, NTC, false, true, false, false><<<grid, block, 0, st>>>(a);
+    } else if (a.sh.lds_frontier) {
+        if constexpr (P == kBF16) {
+            if (a.sh.cross_wave)
+                fwd_kernel<P, D, NTC, true, false, false, true><<<grid, block, 0, st>>>(a);
+            else if (a.g.lx == 16 * NTC)
+                fwd_kernel<P, D, NTC, false, false, true, true><<<grid, block, 0, st>>>(a);
+            else
+                fwd_kernel<P, D, NTC, false, false, false, true><<<grid, block, 0, st>>>(a);
+        }
     } else {
-        fwd_kernel<P, D, NTC, false, false, false><<<grid, block, 0, st>>>(a);
+        if (a.sh.cross_wave)
+            fwd_kernel<P, D, NTC, true, false, false, false><<<grid, block, 0, st>>>(a);
+        else if (a.g.lx == 16 * NTC)
+            fwd_kernel<P, D, NTC, false, false, true, false><<<grid, block, 0, st>>>(a);
+        else
+            fwd_kernel<P, D, NTC, false, false, false, false><<<grid, block, 0, st>>>(a);
     }
     return (int)hipGetLastError();
 }

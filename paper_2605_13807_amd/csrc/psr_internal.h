@@ -67,6 +67,7 @@ struct FwdShape {
     int cols;         // columns per workgroup = waves * ntc * 16
     int seqs;         // sequences per workgroup = cols / lx
     int cross_wave;   // some sequence row spans a wave boundary
+    int lds_frontier; // the row frontier is kept in LDS (BF16 when it fits)
 };
 FwdShape fwd_shape(const Geom& g);
 
