@@ -240,13 +240,17 @@ __device__ inline float carry_apply(float b, float a, float B) {
 
 // GELU(x) = x Phi(x) = max(x, 0) - |x| p(x) with the Gaussian tail
 // p(x) = erfc(|x|/sqrt 2)/2 ~ t Ph(t) 2^(-C x^2), t = 1/(1 + S|x|)
-// (coefficients fitted by gen_gelu_fit.py).
+// (coefficients fitted by gen_gelu_fit.py).  DEG 5 is accurate to float32;
+// DEG 4 (abs. error ~1e-7) serves outputs that are rounded to bfloat16 next.
+template <int DEG = 5>
 __device__ inline float gelu_tail(float x) {
+    const float* P = (DEG == 5) ? kGeluP : kGeluP4;
+    const float S = (DEG == 5) ? kGeluS : kGeluS4;
     const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(ax, kGeluS, 1.0f));
-    float q = kGeluP[0];
+    const float t = __builtin_amdgcn_rcpf(fmaf(ax, S, 1.0f));
+    float q = P[0];
 #pragma unroll
-    for (int k = 1; k <= PSR_GELU_DEG; ++k) q = fmaf(q, t, kGeluP[k]);
+    for (int k = 1; k <= DEG; ++k) q = fmaf(q, t, P[k]);
     const float p = (t * q) * __builtin_amdgcn_exp2f((x * x) * -kGeluC);
     // max(x, 0) on the bit pattern: a negative float is a negative int32
     const float xp = __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
@@ -324,23 +328,23 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
             }
         }
     }
-    float sA[4], sB[4];   // chunk aggregates -> inclusive over chunks 0..lane of the DPP row
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        sA[i] = A[NTC - 1][i];
-        sB[i] = Bv[NTC - 1][i];
-    }
+    // chunk aggregates -> inclusive over chunks 0..lane of the DPP row (in place: the
+    // last column's map is not needed again, because the inclusive value is its h)
+    float (&sA)[4] = A[NTC - 1];
+    float (&sB)[4] = Bv[NTC - 1];
     row_scan4(sA, sB);
     if constexpr (!CROSS) {
+        // no carry enters a wave: lane 0 of a DPP row starts a sequence row
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
 #pragma unroll
-            for (int c = 0; c < NTC; ++c) h[c][i] = carry_apply(Bv[c][i], A[c][i], sB[i]);
+            for (int c = 0; c + 1 < NTC; ++c) h[c][i] = carry_apply(Bv[c][i], A[c][i], sB[i]);
+            h[NTC - 1][i] = sB[i];
+        }
     } else {
-    float X[4];   // carry entering this lane's chunk
+        float X[4];   // carry entering this lane's chunk from the lanes before it
 #pragma unroll
-    for (int i = 0; i < 4; ++i) X[i] = dpp0<0x111>(sB[i]);
-    {
+        for (int i = 0; i < 4; ++i) X[i] = dpp0<0x111>(sB[i]);
         const int buf = mt & 1;
         if (r16 == 15) {
 #pragma unroll
@@ -355,13 +359,11 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
             const float Xa = dpp1<0x111>(sA[i]);   // product of the multipliers before this chunk
             float W = 0.0f;                        // carry entering this wave
             for (int w = 0; w < wave; ++w) W = fmaf(xw[buf][w][4 * g + i][0], W, xw[buf][w][4 * g + i][1]);
-            X[i] = fmaf(Xa, W, X[i]);
+            const float Xt = fmaf(Xa, W, X[i]);
+#pragma unroll
+            for (int c = 0; c + 1 < NTC; ++c) h[c][i] = fmaf(A[c][i], Xt, Bv[c][i]);
+            h[NTC - 1][i] = fmaf(sA[i], W, sB[i]);
         }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < NTC; ++c) h[c][i] = fmaf(A[c][i], X[i], Bv[c][i]);
     }
 }
 
@@ -628,6 +630,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             };
             // GEMM2 operands of tile mt: fragments, the seed (layer 0: table row of D u;
             // else the residual row, zero for layer 1) and the head rows (last layer)
+            uint2 rhold[NTC];   // second half of the last 16-byte residual read
             auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC]) {
                 if constexpr (!CHAIN) {
 #pragma unroll
@@ -641,7 +644,16 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
                             if constexpr (P == kBF16) {
-                                const uint2 v = *reinterpret_cast<const uint2*>(rsrc[c] + 8 * mt);
+                                // 16-byte reads (conflict-free on the padded rows) cover two tiles;
+                                // tiles are fetched in order, so an odd tile uses the held half
+                                uint2 v;
+                                if ((mt & 1) == 0) {
+                                    const uint4 q = *reinterpret_cast<const uint4*>(rsrc[c] + 8 * mt);
+                                    v = uint2{q.x, q.y};
+                                    rhold[c] = uint2{q.z, q.w};
+                                } else {
+                                    v = rhold[c];
+                                }
                                 so[c] = f32x4{__builtin_bit_cast(float, v.x << 16), __builtin_bit_cast(float, v.x & 0xFFFF0000u),
                                               __builtin_bit_cast(float, v.y << 16), __builtin_bit_cast(float, v.y & 0xFFFF0000u)};
                             } else {
@@ -749,8 +761,10 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     if constexpr (!LAST) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
-                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[sl][c][0]), gelu_tail(ao[sl][c][1]));
-                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[sl][c][2]), gelu_tail(ao[sl][c][3]));
+                            // the next layer's input is rounded to bfloat16 on the BF16 path
+                            constexpr int GD = (P == kBF16) ? 4 : 5;
+                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail<GD>(ao[sl][c][0]), gelu_tail<GD>(ao[sl][c][1]));
+                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail<GD>(ao[sl][c][2]), gelu_tail<GD>(ao[sl][c][3]));
                             if constexpr (PF) pin_tile<P, D>(xn[c], mt);
                         }
                     } else {
