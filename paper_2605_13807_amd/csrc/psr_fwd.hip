@@ -608,9 +608,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
             // GEMM1 operands of tile mt: fragments and the accumulator seeds
             // (layer 0: table rows of the site's state; else the biases)
-            auto fetch1 = [&](int mt, AT (&w)[NM1_][NA], f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
-#pragma unroll
-                for (int m = 0; m < NM1; ++m) load_a<P, D>(w[m], m1[m], mt, lane);
+            auto seeds1 = [&](int mt, f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
                 if constexpr (FIRST) {
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
@@ -628,13 +626,16 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     }
                 }
             };
+            auto fetch1 = [&](int mt, AT (&w)[NM1_][NA], f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
+#pragma unroll
+                for (int m = 0; m < NM1; ++m) load_a<P, D>(w[m], m1[m], mt, lane);
+                seeds1(mt, sz, sh);
+            };
             // GEMM2 operands of tile mt: fragments, the seed (layer 0: table row of D u;
             // else the residual row, zero for layer 1) and the head rows (last layer)
             uint2 rhold[NTC];   // second half of the last 16-byte residual read
-            auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC]) {
+            auto seeds2 = [&](int mt, f32x4 (&so)[NTC]) {
                 if constexpr (!CHAIN) {
-#pragma unroll
-                    for (int m = 0; m < NM2; ++m) load_a<P, D>(w[m], m2[m], mt, lane);
                     if constexpr (FIRST) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c)
@@ -663,12 +664,23 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     }
                 }
             };
+            auto fetch2 = [&](int mt, AT (&w)[NM2][NA], f32x4 (&so)[NTC]) {
+                if constexpr (!CHAIN) {
+#pragma unroll
+                    for (int m = 0; m < NM2; ++m) load_a<P, D>(w[m], m2[m], mt, lane);
+                    seeds2(mt, so);
+                }
+            };
 
             // Two operand slots per phase.  With PF the phases are software-pipelined:
             // iteration mt issues the MFMAs of tile mt+1, loads the operands of tile
             // mt+2 and then runs the VALU epilogue of tile mt, so that the matrix core
             // works while the VALU forms the previous tile's outputs.
             constexpr int NSL = PF ? 2 : 1;
+            // Without PF the fragments go through a ring of two single-matrix slots:
+            // the next matrix (of this tile, the next tile or the next phase) loads
+            // while the current matrix's MFMAs run.  Stage q counts matrices.
+            AT wm[PF ? 1 : 2][NA];
             AT w1[NSL][NM1_][NA];
             f32x4 s1z[NSL][NTC], s1h[NSL][NTC];
             AT w2[NSL][NM2][NA];
@@ -699,7 +711,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 for (int c = 0; c < NTC; ++c) {
                     set_pair<P, D>(hb[c], 4 * mt, h[c][0], h[c][1]);
                     set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
-                    if constexpr (PF) pin_tile<P, D>(hb[c], mt);
+                    pin_tile<P, D>(hb[c], mt);
                     if constexpr (CHAIN) {   // head reads h directly
                         const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
                         const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
@@ -716,6 +728,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 fetch1(0, w1[0], s1z[0], s1h[0]);
                 fetch1(1, w1[NSL - 1], s1z[NSL - 1], s1h[NSL - 1]);
                 issue1(0);
+            } else if constexpr (NM1 > 0) {
+                load_a<P, D>(wm[0], m1[0], 0, lane);
             }
 #pragma unroll
             for (int mt = 0; mt < NMT; ++mt) {
@@ -729,9 +743,33 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     valu1(mt, cs);
                     __builtin_amdgcn_sched_barrier(0);
                 } else {
-                    fetch1(mt, w1[0], s1z[0], s1h[0]);
-                    issue1(0);
+                    seeds1(mt, s1z[0], s1h[0]);
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c) {
+                        az[0][c] = s1z[0][c];
+                        ah[0][c] = s1h[0][c];
+                    }
+#pragma unroll
+                    for (int m = 0; m < NM1; ++m) {
+                        const int sl = (mt * NM1 + m) & 1;
+                        if (m + 1 < NM1)
+                            load_a<P, D>(wm[sl ^ 1], m1[m + 1], mt, lane);
+                        else if (mt + 1 < NMT)
+                            load_a<P, D>(wm[sl ^ 1], m1[0], mt + 1, lane);
+                        else if constexpr (!CHAIN)
+                            load_a<P, D>(wm[sl ^ 1], m2[0], 0, lane);
+                        if constexpr (FIRST)
+                            mma_a<P, D, NTC>(ah[0], wm[sl], hv);
+                        else if (m == 0)
+                            mma_a<P, D, NTC>(az[0], wm[sl], u);
+                        else if (m == 1)
+                            mma_a<P, D, NTC>(ah[0], wm[sl], u);
+                        else
+                            mma_a<P, D, NTC>(ah[0], wm[sl], hv);
+                    }
+                    if constexpr (CHAIN && NM1 == 0) (void)wm;
                     valu1(mt, 0);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             if constexpr (CHAIN) return;
@@ -765,7 +803,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                             constexpr int GD = (P == kBF16) ? 4 : 5;
                             set_pair<P, D>(xn[c], 4 * mt, gelu_tail<GD>(ao[sl][c][0]), gelu_tail<GD>(ao[sl][c][1]));
                             set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail<GD>(ao[sl][c][2]), gelu_tail<GD>(ao[sl][c][3]));
-                            if constexpr (PF) pin_tile<P, D>(xn[c], mt);
+                            pin_tile<P, D>(xn[c], mt);
                         }
                     } else {
                         const f32x4 hw0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
@@ -778,7 +816,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                                 l0[c] = fmaf(hw0[i], x, l0[c]);
                                 l1[c] = fmaf(hw1[i], x, l1[c]);
                             }
-                            if constexpr (PF) pin2(l0[c], l1[c]);
+                            pin2(l0[c], l1[c]);
                         }
                     }
                 };
@@ -792,9 +830,23 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         valu2(mt, cs);
                         __builtin_amdgcn_sched_barrier(0);
                     } else {
-                        fetch2(mt, w2[0], s2[0]);
-                        issue2(0);
+                        seeds2(mt, s2[0]);
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) ao[0][c] = s2[0][c];
+#pragma unroll
+                        for (int m = 0; m < NM2; ++m) {
+                            const int sl = (NMT * NM1 + mt * NM2 + m) & 1;
+                            if (m + 1 < NM2)
+                                load_a<P, D>(wm[sl ^ 1], m2[m + 1], mt, lane);
+                            else if (mt + 1 < NMT)
+                                load_a<P, D>(wm[sl ^ 1], m2[0], mt + 1, lane);
+                            if (FIRST || m == 1)
+                                mma_a<P, D, NTC>(ao[0], wm[sl], hb);
+                            else
+                                mma_a<P, D, NTC>(ao[0], wm[sl], u);
+                        }
                         valu2(mt, 0);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
                 if constexpr (!LAST) {
