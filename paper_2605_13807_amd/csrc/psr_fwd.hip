@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             }
 
             // source of the residual h^(l-1) (layers >= 2): this row's frontier of layer l-1;
-            // layers 0 and 1 read the zero row (LDS frontier) or scale by 0 (global frontier)
+            // layer 1 reads the zero row (LDS frontier) or scales what it reads by 0 (global frontier)
             const uint8_t* rsrc[NTC];
             float rs = 1.0f;
 #pragma unroll
@@ -657,6 +657,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                                 }
                                 so[c] = f32x4{__builtin_bit_cast(float, v.x << 16), __builtin_bit_cast(float, v.x & 0xFFFF0000u),
                                               __builtin_bit_cast(float, v.y << 16), __builtin_bit_cast(float, v.y & 0xFFFF0000u)};
+                                if constexpr (!LDSF) so[c] = so[c] * rs;   // layer 1 has no residual
                             } else {
                                 so[c] = *reinterpret_cast<const f32x4*>(rsrc[c] + 16 * mt) * rs;
                             }

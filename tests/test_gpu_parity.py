@@ -140,6 +140,9 @@ LOGPSI_CASES = [
     (1, 32, 32, 3, 128, 1, 9),
     (1, 52, 52, 4, 256, 0, 2),     # the largest lattice
     (1, 52, 52, 4, 256, 1, 2),
+    (1, 60, 3, 4, 256, 1, 3),      # BF16 row frontier too large for LDS: kept in global memory
+    (1, 64, 2, 2, 64, 1, 5),       # rows of exactly one DPP row of 4-column chunks
+    (1, 16, 3, 2, 256, 1, 4),      # rows of exactly one DPP row of 1-column chunks
 ]
 
 
