@@ -567,6 +567,13 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             }
         }
 
+        // GEMM1 operand slots (fragments and seeds of two tiles), at row scope so that a
+        // layer can load the next layer's first two tiles during its last output tiles
+        constexpr bool PFK = 3 * NA <= 12;   // layers >= 1 run the pipelined path
+        AT w1r[2][3][NA];
+        f32x4 s1zr[2][NTC], s1hr[2][NTC];
+        bool pre1 = false;   // the next layer's tiles 0 and 1 are in w1r / s1zr / s1hr
+
         // One layer.  FIRST: u is the one-hot layer-0 input (tables);  LAST: x feeds the head.
         // Inside a layer there is no branch between the output tiles; the operands of
         // the next tile (weight fragments, accumulator seeds) are loaded while the
@@ -576,7 +583,6 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             constexpr bool LAST = decltype(last_c)::value;
             constexpr int NM1 = CHAIN ? 0 : (FIRST ? 1 : 3);       // GEMM1 matrices: (W_hV) or (W_z, W_hu, W_hV)
             constexpr int NM2 = CHAIN ? 1 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
-            constexpr int NM1_ = NM1 ? NM1 : 1;
             // prefetch one tile ahead when the fragments of a tile are few registers
             constexpr bool PF = NM1 * NA <= 12;
             const uint8_t* m1[3];
@@ -626,7 +632,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     }
                 }
             };
-            auto fetch1 = [&](int mt, AT (&w)[NM1_][NA], f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
+            auto fetch1 = [&](int mt, AT (&w)[3][NA], f32x4 (&sz)[NTC], f32x4 (&sh)[NTC]) {
 #pragma unroll
                 for (int m = 0; m < NM1; ++m) load_a<P, D>(w[m], m1[m], mt, lane);
                 seeds1(mt, sz, sh);
@@ -677,29 +683,33 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             // iteration mt issues the MFMAs of tile mt+1, loads the operands of tile
             // mt+2 and then runs the VALU epilogue of tile mt, so that the matrix core
             // works while the VALU forms the previous tile's outputs.
-            constexpr int NSL = PF ? 2 : 1;
+            constexpr int NSL = PF ? 2 : 1;   // accumulator slots
+            // operand (fragments + seeds) slots: tile mt+NWS loads during tile mt (a third
+            // slot measured slower: the extra registers become accumulator-register moves)
+            constexpr int NWS = PF ? 2 : 1;
             // Without PF the fragments go through a ring of two single-matrix slots:
             // the next matrix (of this tile, the next tile or the next phase) loads
             // while the current matrix's MFMAs run.  Stage q counts matrices.
             AT wm[PF ? 1 : 2][NA];
-            AT w1[NSL][NM1_][NA];
-            f32x4 s1z[NSL][NTC], s1h[NSL][NTC];
-            AT w2[NSL][NM2][NA];
-            f32x4 s2[NSL][NTC];
+            auto& w1 = w1r;
+            auto& s1z = s1zr;
+            auto& s1h = s1hr;
+            AT w2[NWS][NM2][NA];
+            f32x4 s2[NWS][NTC];
             f32x4 az[NSL][NTC], ah[NSL][NTC], ao[NSL][NTC];
 
-            auto issue1 = [&](int sl) {
+            auto issue1 = [&](int sl, int ws) {   // accumulator slot, operand slot
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
-                    az[sl][c] = s1z[sl][c];
-                    ah[sl][c] = s1h[sl][c];
+                    az[sl][c] = s1z[ws][c];
+                    ah[sl][c] = s1h[ws][c];
                 }
                 if constexpr (FIRST) {
-                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah[sl], w1[sl][0], hv);
+                    if constexpr (!CHAIN) mma_a<P, D, NTC>(ah[sl], w1[ws][0], hv);
                 } else {
-                    mma_a<P, D, NTC>(az[sl], w1[sl][0], u);
-                    mma_a<P, D, NTC>(ah[sl], w1[sl][1], u);
-                    mma_a<P, D, NTC>(ah[sl], w1[sl][2], hv);
+                    mma_a<P, D, NTC>(az[sl], w1[ws][0], u);
+                    mma_a<P, D, NTC>(ah[sl], w1[ws][1], u);
+                    mma_a<P, D, NTC>(ah[sl], w1[ws][2], hv);
                 }
             };
             Frag hb[NTC][NK];
@@ -726,9 +736,17 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             };
 
             if constexpr (PF) {
-                fetch1(0, w1[0], s1z[0], s1h[0]);
-                fetch1(1, w1[NSL - 1], s1z[NSL - 1], s1h[NSL - 1]);
-                issue1(0);
+                if (!pre1) {
+#pragma unroll
+                    for (int t = 0; t < NWS; ++t) {
+                        if (t < NMT)
+                            fetch1(t, w1[t], s1z[t], s1h[t]);
+                        else if constexpr (!CHAIN)
+                            fetch2(t - NMT, w2[t - NMT], s2[t - NMT]);
+                    }
+                }
+                pre1 = false;
+                issue1(0, 0);
             } else if constexpr (NM1 > 0) {
                 load_a<P, D>(wm[0], m1[0], 0, lane);
             }
@@ -736,11 +754,14 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             for (int mt = 0; mt < NMT; ++mt) {
                 if constexpr (PF) {
                     const int cs = mt & 1, ns = cs ^ 1;
-                    if (mt + 1 < NMT) issue1(ns);
-                    if (mt + 2 < NMT)
-                        fetch1(mt + 2, w1[cs], s1z[cs], s1h[cs]);
-                    else if constexpr (!CHAIN)
-                        fetch2(mt + 2 - NMT, w2[cs], s2[cs]);
+                    if (mt + 1 < NMT) issue1(ns, (mt + 1) % NWS);
+                    // tile mt+3 reuses the operand slot of tile mt (its MFMAs are issued)
+                    const int t = mt + NWS;
+                    if (t < NMT)
+                        fetch1(t, w1[mt % NWS], s1z[mt % NWS], s1h[mt % NWS]);
+                    else if (t - NMT < NWS && t - NMT < NMT) {
+                        if constexpr (!CHAIN) fetch2(t - NMT, w2[(t - NMT) % NWS], s2[(t - NMT) % NWS]);
+                    }
                     valu1(mt, cs);
                     __builtin_amdgcn_sched_barrier(0);
                 } else {
@@ -790,11 +811,11 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
                 // ---- x = GELU(C h + D u + s); the last layer feeds the head
                 Frag xn[NTC][LAST ? 1 : NK];
-                auto issue2 = [&](int sl) {
+                auto issue2 = [&](int sl, int ws) {   // accumulator slot, operand slot
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c) ao[sl][c] = s2[sl][c];
-                    if constexpr (!FIRST) mma_a<P, D, NTC>(ao[sl], w2[sl][0], u);
-                    mma_a<P, D, NTC>(ao[sl], w2[sl][NM2 - 1], hb);
+                    for (int c = 0; c < NTC; ++c) ao[sl][c] = s2[ws][c];
+                    if constexpr (!FIRST) mma_a<P, D, NTC>(ao[sl], w2[ws][0], u);
+                    mma_a<P, D, NTC>(ao[sl], w2[ws][NM2 - 1], hb);
                 };
                 auto valu2 = [&](int mt, int sl) {
                     if constexpr (!LAST) {
@@ -821,13 +842,30 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         }
                     }
                 };
-                if constexpr (PF) issue2(0);
+                if constexpr (PF) issue2(0, 0);
 #pragma unroll
                 for (int mt = 0; mt < NMT; ++mt) {
                     if constexpr (PF) {
                         const int cs = mt & 1, ns = cs ^ 1;
-                        if (mt + 1 < NMT) issue2(ns);
-                        if (mt + 2 < NMT) fetch2(mt + 2, w2[cs], s2[cs]);
+                        if (mt + 1 < NMT) issue2(ns, (mt + 1) % NWS);
+                        if (mt + NWS < NMT) {
+                            fetch2(mt + NWS, w2[mt % NWS], s2[mt % NWS]);
+                        } else if constexpr (PFK && !LAST) {
+                            // the next layer's tiles 0 and 1 (layer l+1 >= 1: W_z, W_hu, W_hV, biases)
+                            const int t = mt + NWS - NMT;
+                            const uint8_t* mn[3] = {a.frag + a.pl.frag[l + 1][0], a.frag + a.pl.frag[l + 1][1],
+                                                    a.frag + a.pl.frag[l + 1][2]};
+#pragma unroll
+                            for (int m = 0; m < 3; ++m) load_a<P, D>(w1[t][m], mn[m], t, lane);
+                            const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l + 1] + g * NS + 4 * t);
+                            const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l + 1] + g * NS + 4 * t);
+#pragma unroll
+                            for (int c = 0; c < NTC; ++c) {
+                                s1z[t][c] = bz;
+                                s1h[t][c] = bh;
+                            }
+                            pre1 = true;
+                        }
                         valu2(mt, cs);
                         __builtin_amdgcn_sched_barrier(0);
                     } else {
