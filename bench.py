@@ -242,8 +242,22 @@ def main() -> int:
                          f"(float64 numpy forward) + 1 per-sample gradient (float64 torch autograd); "
                          f"{t_fwd + t_bwd:.1f} s"}
         e_gpu = r["out"][0][:n_s].cpu().numpy()
-        err = {"eloc_rel_err_vs_fp64_oracle": float(np.max(np.abs(e_gpu - e_ref) / np.maximum(np.abs(e_ref), 1.0))),
-               "samples_checked": n_s}
+
+        def rel(e):
+            return float(np.max(np.abs(e - e_ref) / np.maximum(np.abs(e_ref), 1.0)))
+
+        err = {"eloc_rel_err_vs_fp64_oracle": rel(e_gpu), "samples_checked": n_s}
+        if prec == P.BF16:
+            # the same sample through the oracle's bfloat16 reading: how much of the
+            # error above is the precision's (the GPU follows the reading)
+            e_rd = OH.local_energy(lambda c: OM.logpsi(th_np, c, om, bf16=True), oh, sub)
+            err["eloc_rel_err_bf16_reading_vs_fp64"] = rel(e_rd)
+            err["eloc_rel_err_vs_bf16_reading"] = float(
+                np.max(np.abs(e_gpu - e_rd) / np.maximum(np.abs(e_rd), 1.0)))
+            # the FP32 path on the same sample
+            m32 = P.Model(P.SNAKE_2D, L, L, nl, d, P.FP32)
+            e32, _, _ = P.local_energy(m32, r["th"], r["H"], r["s"][:n_s])
+            err["eloc_rel_err_fp32_path_vs_fp64"] = rel(e32.cpu().numpy())
         print(f"# cpu oracle: {cpu['value']:.4e} site-evals/s ({t_fwd + t_bwd:.1f} s)", file=sys.stderr, flush=True)
 
     line = {
