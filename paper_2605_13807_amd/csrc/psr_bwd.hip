@@ -188,14 +188,28 @@ __device__ float row_forward(const BwdArgs& a, const Buf& b, const uint32_t* w, 
         __syncthreads();
         for (int e = tid; e < lx * d; e += T) Zs[e] = sigm(Zs[e]);
         __syncthreads();
-        // sequential recurrence along the snake row, one thread per unit
+        // sequential recurrence along the snake row, one thread per unit; the operands
+        // of a block of 8 sites are loaded before the block's dependent updates
         for (int m = tid; m < d; m += T) {
             float h = 0.0f;
-            for (int s = 0; s < lx; ++s) {
-                const int i = (j & 1) ? lx - 1 - s : s;
-                const float z = Zs[i * d + m];
-                h = z * h + (1.0f - z) * HTs[i * d + m];
-                Hrow[i * d + m] = h;
+            for (int s0 = 0; s0 < lx; s0 += 8) {
+                float zb[8], tb[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int s = min(s0 + q, lx - 1);
+                    const int i = (j & 1) ? lx - 1 - s : s;
+                    zb[q] = Zs[i * d + m];
+                    tb[q] = HTs[i * d + m];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int s = s0 + q;
+                    if (s < lx) {
+                        const int i = (j & 1) ? lx - 1 - s : s;
+                        h = zb[q] * h + (1.0f - zb[q]) * tb[q];
+                        Hrow[i * d + m] = h;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -233,12 +247,24 @@ __device__ float row_forward(const BwdArgs& a, const Buf& b, const uint32_t* w, 
     }
     // head on X = x^(nl) (chain: h)
     const int64_t oWo = G.chain ? a.off[4] : a.off[6 * nl], obo = oWo + 2 * d;
-    for (int i = tid; i < lx; i += T) {
-        float l0 = a.theta[obo], l1 = a.theta[obo + 1];
-        for (int k = 0; k < d; ++k) {
-            l0 = fmaf(a.theta[oWo + k], X[i * d + k], l0);
-            l1 = fmaf(a.theta[oWo + d + k], X[i * d + k], l1);
+    // logits: 8 threads per site, each a d/8 slice of the products, then a shuffle sum
+    for (int i0 = 0; i0 < lx; i0 += T / 8) {
+        const int i = i0 + tid / 8, part = tid % 8;
+        float l0 = 0.0f, l1 = 0.0f;
+        if (i < lx) {
+            for (int k = part; k < d; k += 8) {
+                l0 = fmaf(a.theta[oWo + k], X[i * d + k], l0);
+                l1 = fmaf(a.theta[oWo + d + k], X[i * d + k], l1);
+            }
         }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            l0 += __shfl_xor(l0, o, 8);
+            l1 += __shfl_xor(l1, o, 8);
+        }
+        if (i >= lx || part != 0) continue;
+        l0 += a.theta[obo];
+        l1 += a.theta[obo + 1];
         const int own = spin_at(w, j * lx + i);
         const float mx = fmaxf(l0, l1);
         const float lse = mx + logf(expf(l0 - mx) + expf(l1 - mx));
@@ -340,19 +366,32 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
                 // reverse scan along the snake row, one thread per unit
                 for (int m = tid; m < d; m += T) {
                     float lam = 0.0f, znext = 0.0f;
-                    for (int sidx = lx - 1; sidx >= 0; --sidx) {
-                        const int i = (j & 1) ? lx - 1 - sidx : sidx;
-                        lam = b.LAM[i * d + m] + znext * lam;
-                        const float z = Z[i * d + m];
-                        float hprev = 0.0f;
-                        if (sidx > 0) {
-                            const int ip = (j & 1) ? lx - sidx : sidx - 1;
-                            hprev = Hh[ip * d + m];
+                    for (int s1 = lx - 1; s1 >= 0; s1 -= 8) {
+                        // operands of 8 sites (snake positions s1, s1-1, ...) first
+                        float gl[8], zb[8], tb[8], hp[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int sidx = max(s1 - q, 0);
+                            const int i = (j & 1) ? lx - 1 - sidx : sidx;
+                            const int ip = (j & 1) ? lx - sidx : sidx - 1;   // snake predecessor
+                            gl[q] = b.LAM[i * d + m];
+                            zb[q] = Z[i * d + m];
+                            tb[q] = HT[i * d + m];
+                            hp[q] = (sidx > 0) ? Hh[ip * d + m] : 0.0f;
                         }
-                        const float gz = lam * (hprev - HT[i * d + m]);
-                        ght[i * d + m] = lam * (1.0f - z);
-                        gzp[i * d + m] = gz * z * (1.0f - z);
-                        znext = z;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int sidx = s1 - q;
+                            if (sidx >= 0) {
+                                const int i = (j & 1) ? lx - 1 - sidx : sidx;
+                                lam = gl[q] + znext * lam;
+                                const float z = zb[q];
+                                const float gz = lam * (hp[q] - tb[q]);
+                                ght[i * d + m] = lam * (1.0f - z);
+                                gzp[i * d + m] = gz * z * (1.0f - z);
+                                znext = z;
+                            }
+                        }
                     }
                 }
                 __syncthreads();
@@ -392,22 +431,28 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
                 gemm(d, d, S, MA{b.XIN + L, 1, d}, MB{b.GHT + L, d, 1}, MC{Orow + oWh, 1, ldh}, true);
                 gemm(d, d, S, MA{b.XIN + L, 1, d}, MB{b.GPRE + L, d, 1}, MC{Orow + a.off[6 * l + 5], 1, du}, true);
             } else {
-                // one-hot layer-0 input (chain: previous spin)
-                for (int e = tid; e < d * du; e += T) {
-                    const int m = e / du, k = e - m * du;
-                    float gw = 0.0f, gz = 0.0f, gd = 0.0f;
-                    for (int rr = 0; rr < nrow; ++rr) {
-                        const int64_t bs = cidx(a, rr, 0);
-                        for (int i = 0; i < lx; ++i) {
-                            if (u0_val(G, w, j0 + rr, i, k) == 0.0f) continue;
-                            gw += b.GHT[bs + i * d + m];
-                            gz += b.GZP[bs + i * d + m];
-                            if (!G.chain) gd += b.GPRE[bs + i * d + m];
+                // one-hot layer-0 input (chain: previous spin): each site adds its
+                // adjoints to the (at most two) input columns that are 1 there
+                for (int m = tid; m < d; m += T) {
+                    float gw[4] = {0.f, 0.f, 0.f, 0.f}, gz[4] = {0.f, 0.f, 0.f, 0.f}, gd[4] = {0.f, 0.f, 0.f, 0.f};
+                    for (int e = 0; e < S; ++e) {
+                        const int rr = e / lx, i = e - rr * lx;
+                        const float vh = b.GHT[L + (int64_t)e * d + m], vz = b.GZP[L + (int64_t)e * d + m];
+                        const float vp = G.chain ? 0.0f : b.GPRE[L + (int64_t)e * d + m];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (k < du && u0_val(G, w, j0 + rr, i, k) != 0.0f) {
+                                gw[k] += vh;
+                                gz[k] += vz;
+                                gd[k] += vp;
+                            }
                         }
                     }
-                    Orow[oWh + (int64_t)m * ldh + k] += gw;
-                    Orow[oWz + (int64_t)m * du + k] += gz;
-                    if (!G.chain) Orow[a.off[6 * l + 5] + (int64_t)m * du + k] += gd;
+                    for (int k = 0; k < du; ++k) {
+                        Orow[oWh + (int64_t)m * ldh + k] += gw[k];
+                        Orow[oWz + (int64_t)m * du + k] += gz[k];
+                        if (!G.chain) Orow[a.off[6 * l + 5] + (int64_t)m * du + k] += gd[k];
+                    }
                 }
             }
             if (!G.chain) {
@@ -417,6 +462,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
             // biases
             for (int m = tid; m < d; m += T) {
                 float sz = 0.0f, sh = 0.0f;
+#pragma unroll 8
                 for (int e = 0; e < S; ++e) {
                     sz += b.GZP[L + (int64_t)e * d + m];
                     sh += b.GHT[L + (int64_t)e * d + m];
@@ -427,21 +473,26 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
             __syncthreads();
         }
         // head
-        for (int e = tid; e < 2 * d + 2; e += T) {
-            float acc = 0.0f;
-            for (int rr = 0; rr < nrow; ++rr) {
-                const int64_t bs = cidx(a, rr, nl - 1);
-                for (int i = 0; i < lx; ++i) {
-                    if (e < 2 * d) {
-                        const int k = e / d, m = e - k * d;
-                        const float x = G.chain ? b.H[bs + i * d + m] : gelu(b.PRE[bs + i * d + m]);
-                        acc = fmaf(b.GLOG[(rr * lx + i) * 2 + k], x, acc);
-                    } else {
-                        acc += b.GLOG[(rr * lx + i) * 2 + (e - 2 * d)];
-                    }
+        // head: per unit m both logits' rows (x computed once per site), then the biases
+        {
+            const int64_t Lh = cidx(a, 0, nl - 1);
+            const int S = (j1 - j0) * lx;
+            for (int m = tid; m < d; m += T) {
+                float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll 4
+                for (int e = 0; e < S; ++e) {
+                    const float x = G.chain ? b.H[Lh + (int64_t)e * d + m] : gelu(b.PRE[Lh + (int64_t)e * d + m]);
+                    a0 = fmaf(b.GLOG[e * 2], x, a0);
+                    a1 = fmaf(b.GLOG[e * 2 + 1], x, a1);
                 }
+                Orow[oWo + m] += a0;
+                Orow[oWo + d + m] += a1;
             }
-            Orow[oWo + e] += acc;
+            if (tid < 2) {
+                float acc = 0.0f;
+                for (int e = 0; e < S; ++e) acc += b.GLOG[e * 2 + tid];
+                Orow[oWo + 2 * d + tid] += acc;
+            }
         }
         __syncthreads();
     }
