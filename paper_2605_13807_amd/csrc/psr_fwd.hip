@@ -470,7 +470,9 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     const int64_t q0 = a.q_begin + (int64_t)blockIdx.x * seqs;
     if (q0 >= q_end) return;   // uniform across the workgroup
     if constexpr (LDSF) {
-        for (int e = threadIdx.x; e < ZOFF / 4; e += blockDim.x) reinterpret_cast<uint32_t*>(fl)[e] = 0u;
+        // the zero row, and the frontier itself: row 0 reads it as h_V before it is written
+        const int nw = (ZOFF + a.sh.seqs * G.nl * G.lx * PITCH) / 16;
+        for (int e = threadIdx.x; e < nw; e += blockDim.x) reinterpret_cast<uint4*>(fl)[e] = uint4{0u, 0u, 0u, 0u};
     }
 
     // per-column constants (column = chunk position c of this lane), kept in 32-bit fields
@@ -584,7 +586,11 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             constexpr int NM1 = CHAIN ? 0 : (FIRST ? 1 : 3);       // GEMM1 matrices: (W_hV) or (W_z, W_hu, W_hV)
             constexpr int NM2 = CHAIN ? 1 : (FIRST ? 1 : 2);       // GEMM2 matrices: (C) or (D, C)
             // prefetch one tile ahead when the fragments of a tile are few registers
-            constexpr bool PF = NM1 * NA <= 12;
+            // (decided per model, not per layer: a pipelined first layer with large tiles
+            // would hold two slots of fragments for both GEMMs at once)
+            constexpr bool PF = PFK;
+            // layers >= 1 without the pipelined path read h_V from the LDS frontier per tile
+            constexpr bool HVL = LDSF && !PF && !FIRST;
             const uint8_t* m1[3];
             const uint8_t* m2[2];
             if constexpr (FIRST) {
@@ -786,8 +792,19 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                             mma_a<P, D, NTC>(az[0], wm[sl], u);
                         else if (m == 1)
                             mma_a<P, D, NTC>(ah[0], wm[sl], u);
-                        else
+                        else if constexpr (HVL) {
+                            // h_V straight from the LDS frontier, live only for this product
+                            Frag hvt[NTC][NK];
+#pragma unroll
+                            for (int c = 0; c < NTC; ++c) {
+                                const f32x4* src = reinterpret_cast<const f32x4*>(frow[c] + l * fl_stride);
+#pragma unroll
+                                for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) frag_set16<P, D>(hvt[c], k, src[k]);
+                            }
+                            mma_a<P, D, NTC>(ah[0], wm[sl], hvt);
+                        } else {
                             mma_a<P, D, NTC>(ah[0], wm[sl], hv);
+                        }
                     }
                     if constexpr (CHAIN && NM1 == 0) (void)wm;
                     valu1(mt, 0);
@@ -804,8 +821,9 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 #pragma unroll
                     for (int k = 0; k < NK * (int)sizeof(Frag) / 16; ++k) dst[k] = frag_get16<P, D>(hb[c], k);
                 }
-                // the next layer's h_V, in flight during this layer's output
-                if constexpr (!LAST) {
+                // the next layer's h_V, in flight during this layer's output (not needed when
+                // the next layer reads it from the LDS frontier tile by tile)
+                if constexpr (!LAST && !(LDSF && !PFK)) {
                     if (vert) load_hv(l + 1);
                 }
 
