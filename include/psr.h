@@ -158,7 +158,8 @@ int psr_local_energy(const psr_model_desc* m, const float* theta, const psr_hami
  *   O       device float[B][P] or NULL   (out) one gradient row per sample
  *   logpsi  device float[B] or NULL      (out)
  *   w, g    device double[B], double[P]  both NULL or both set: g = sum_s w_s O_s (FP64)
- * At least one of O and g must be set.
+ * At least one of O and g must be set.  The backward runs in FP32 whatever
+ * m->precision is: O is the gradient of the FP32 model (and logpsi its value).
  */
 int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B,
                         float* O, float* logpsi, const double* w, double* g,
