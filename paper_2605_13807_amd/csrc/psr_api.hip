@@ -140,7 +140,7 @@ Prepared prepared_layout(const Geom& g) {
         pl.bias_z[l] = t; t += d;
         pl.bias_h[l] = t; t += d;
     }
-    pl.head_w = t; t += 2 * d;
+    pl.head_w = t; t += d;
     pl.head_b = t; t += 4;
     pl.table_floats = t;
     return pl;

@@ -119,6 +119,15 @@ __global__ void prep_tab0(const float* __restrict__ theta, Tab0Src s, float* __r
     td[p] = dv;
 }
 
+// Head of the two-class log-softmax: w = W_o[0] - W_o[1] (slot order), b = b_o[0] - b_o[1].
+__global__ void prep_head(const float* __restrict__ theta, int64_t src_w, int64_t src_b, int d, float* __restrict__ w,
+                          float* __restrict__ b) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= d) return;
+    w[unit_pos(u, d)] = theta[src_w + u] - theta[src_w + d + u];
+    if (u == 0) b[0] = theta[src_b] - theta[src_b + 1];
+}
+
 __global__ void prep_vec(const float* __restrict__ theta, int64_t src, int d, int rows, float* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows * d) return;
@@ -179,9 +188,7 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
         prep_vec<<<(d + T - 1) / T, T, 0, st>>>(theta, off[6 * l + 3], d, 1, tab + pl.bias_h[l]);
     }
     const int ih = g.chain ? 4 : 6 * g.nl;   // index of W_o in the tensor list
-    prep_vec<<<(2 * d + T - 1) / T, T, 0, st>>>(theta, off[ih], d, 2, tab + pl.head_w);
-    const hipError_t ce = hipMemcpyAsync(tab + pl.head_b, theta + off[ih + 1], 2 * sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (ce != hipSuccess) return (int)ce;
+    prep_head<<<(d + T - 1) / T, T, 0, st>>>(theta, off[ih], off[ih + 1], d, tab + pl.head_w, tab + pl.head_b);
     return (int)hipGetLastError();
 }
 
@@ -210,23 +217,34 @@ __device__ inline float dpp1(float src) {
 // VALU op itself -- B += B' A (v_fmac_f32_dpp), then A *= A' (v_mul_f32_dpp) --
 // so it costs two instructions per map.  Without bound_ctrl a lane whose
 // source lies outside the row is not written, i.e. it composes with the
-// identity map.  Hazards: a DPP read of a VGPR needs two wait states after the
-// VALU write; the leading s_nop covers values written just before the block,
-// inside it every DPP read is at least four instructions after the write, and
-// the trailing s_nop covers DPP reads of A right after the block.
+// identity map.  FULL_A = false leaves A after the last step un-updated, for
+// callers that read only the inclusive B.  Hazards: a DPP read of a VGPR needs
+// two wait states after the VALU write; the leading s_nop covers values written
+// just before the block, inside it every DPP read is at least four instructions
+// after the write, and the trailing s_nop covers DPP reads of A or B right
+// after the block.
+template <bool FULL_A>
 __device__ inline void row_scan4(float (&A)[4], float (&B)[4]) {
-#define PSR_SCAN_STEP(S)                                                   \
+#define PSR_SCAN_B(S)                                                      \
     "v_fmac_f32_dpp %0, %0, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
     "v_fmac_f32_dpp %1, %1, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
     "v_fmac_f32_dpp %2, %2, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_fmac_f32_dpp %3, %3, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_mul_f32_dpp %4, %4, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
-    "v_mul_f32_dpp %5, %5, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
-    "v_mul_f32_dpp %6, %6, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n"  \
+    "v_fmac_f32_dpp %3, %3, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
+#define PSR_SCAN_A(S)                                                     \
+    "v_mul_f32_dpp %4, %4, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_mul_f32_dpp %5, %5, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
+    "v_mul_f32_dpp %6, %6, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
     "v_mul_f32_dpp %7, %7, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
-    asm("s_nop 1\n" PSR_SCAN_STEP("1") PSR_SCAN_STEP("2") PSR_SCAN_STEP("4") PSR_SCAN_STEP("8") "s_nop 1"
-                 : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
-#undef PSR_SCAN_STEP
+    if constexpr (FULL_A)
+        asm("s_nop 1\n" PSR_SCAN_B("1") PSR_SCAN_A("1") PSR_SCAN_B("2") PSR_SCAN_A("2") PSR_SCAN_B("4") PSR_SCAN_A("4")
+            PSR_SCAN_B("8") PSR_SCAN_A("8") "s_nop 1"
+            : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
+    else
+        asm("s_nop 1\n" PSR_SCAN_B("1") PSR_SCAN_A("1") PSR_SCAN_B("2") PSR_SCAN_A("2") PSR_SCAN_B("4") PSR_SCAN_A("4")
+            PSR_SCAN_B("8") "s_nop 1"
+            : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
+#undef PSR_SCAN_A
+#undef PSR_SCAN_B
 }
 
 // h = b + a * (B of lane - 1 in the DPP row), with the neighbour's register read
@@ -274,9 +292,24 @@ struct AOp {
 template <int P, int D, class W>
 __device__ inline void load_a(W& w, const uint8_t* __restrict__ mat, int mt, int lane) {
     typedef typename AOp<P, D>::T T;
-    const T* A = reinterpret_cast<const T*>(mat) + (size_t)mt * AOp<P, D>::N * 64 + lane;
+    constexpr int TILE = AOp<P, D>::N * 64 * (int)sizeof(T);   // bytes of one output tile's fragments
+    // Large tiles (FP32, or d = 256) use buffer loads: the matrix base and the tile
+    // offset stay scalar and the lane offset is one constant vector register, which
+    // frees the registers that per-tile 64-bit addresses would hold (those kernels
+    // spilled without it); the descriptor bounds the matrix (an out-of-range lane
+    // would read zeros).  BF16 at d <= 128 measured faster with plain global loads.
+    constexpr bool BUF = (P == kFP32) || D >= 256;
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(mat), 0, TILE * (D / 16), 0x00020000);
 #pragma unroll
-    for (int k = 0; k < AOp<P, D>::N; ++k) w[k] = A[k * 64];
+        for (int k = 0; k < AOp<P, D>::N; ++k)
+            w[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 1024, mt * TILE, 0));
+    } else {
+        const T* A = reinterpret_cast<const T*>(mat + (size_t)mt * TILE) + lane;
+#pragma unroll
+        for (int k = 0; k < AOp<P, D>::N; ++k) w[k] = A[k * 64];
+    }
 }
 
 // acc[c] += W(tile) * b[c] for the NTC column tiles
@@ -332,7 +365,7 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
     // last column's map is not needed again, because the inclusive value is its h)
     float (&sA)[4] = A[NTC - 1];
     float (&sB)[4] = Bv[NTC - 1];
-    row_scan4(sA, sB);
+    row_scan4<CROSS>(sA, sB);
     if constexpr (!CROSS) {
         // no carry enters a wave: lane 0 of a DPP row starts a sequence row
 #pragma unroll
@@ -392,7 +425,7 @@ __device__ inline void pin_tile(typename MF<P>::Frag (&f)[D / MF<P>::K], int mt)
         asm volatile("" ::"v"(f[4 * mt]), "v"(f[4 * mt + 1]), "v"(f[4 * mt + 2]), "v"(f[4 * mt + 3]));
     }
 }
-__device__ inline void pin2(float& x, float& y) { asm volatile("" : "+v"(x), "+v"(y)); }
+__device__ inline void pin1(float& x) { asm volatile("" : "+v"(x)); }
 
 // Row frontier (h of the previous row, the operand type of the projections):
 // per sequence-local index qi, layer l, physical column i, lane group g, the
@@ -418,6 +451,12 @@ __device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K]
         return __builtin_bit_cast(f32x4, f[k]);
     else
         return f32x4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
+}
+
+// 16 bytes at a uniform float base plus a per-lane byte offset that fits 32 bits
+// (lets the compiler address with a scalar base and a 32-bit vector offset)
+__device__ inline f32x4 ld16(const float* base, uint32_t byte_off) {
+    return *reinterpret_cast<const f32x4*>(reinterpret_cast<const uint8_t*>(base) + byte_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,6 +546,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     for (int c = 0; c < NTC; ++c) keep[c] = (t[c] == 0) ? 0.0f : 1.0f;
 
     const float* tab = a.tab;
+    const uint32_t goff = (uint32_t)(g * NS) * 4u;   // byte offset of this lane's unit group in a d-vector
     float ls[NTC], lc[NTC];
 #pragma unroll
     for (int c = 0; c < NTC; ++c) ls[c] = lc[c] = 0.0f;
@@ -542,9 +582,11 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             else
                 frow[c] = col_ptr<F::ELT, D>(a.frontier, seq_local(c), 0, nl, lx, iph[c], g);
         }
-        float l0[NTC], l1[NTC];   // head logits, accumulated over the last layer's output tiles
+        // logit difference l_0 - l_1 of the head (all a two-class log-softmax needs),
+        // accumulated over the last layer's output tiles
+        float l0[NTC];
 #pragma unroll
-        for (int c = 0; c < NTC; ++c) l0[c] = l1[c] = 0.0f;
+        for (int c = 0; c < NTC; ++c) l0[c] = 0.0f;
 
         // h_V operand of the layer being computed: the previous row's frontier (0 on row 0).
         // Layer 0's is loaded here; layer l+1's is loaded while layer l forms its output.
@@ -624,13 +666,13 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                 if constexpr (FIRST) {
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
-                        const int o = st[c] * D + g * NS + 4 * mt;
-                        sz[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0z + o);
-                        sh[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0h + o);
+                        const int o = st[c] * D + g * NS;
+                        sz[c] = ld16(tab + a.pl.t0z + 4 * mt, (uint32_t)o * 4u);
+                        sh[c] = ld16(tab + a.pl.t0h + 4 * mt, (uint32_t)o * 4u);
                     }
                 } else {
-                    const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l] + g * NS + 4 * mt);
-                    const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l] + g * NS + 4 * mt);
+                    const f32x4 bz = ld16(tab + a.pl.bias_z[l] + 4 * mt, goff);
+                    const f32x4 bh = ld16(tab + a.pl.bias_h[l] + 4 * mt, goff);
 #pragma unroll
                     for (int c = 0; c < NTC; ++c) {
                         sz[c] = bz;
@@ -651,7 +693,7 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     if constexpr (FIRST) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c)
-                            so[c] = *reinterpret_cast<const f32x4*>(tab + a.pl.t0d + st[c] * D + g * NS + 4 * mt);
+                            so[c] = ld16(tab + a.pl.t0d + 4 * mt, (uint32_t)(st[c] * D + g * NS) * 4u);
                     } else {
                         // residual h^(l-1) of this row, from the frontier (layers >= 2)
 #pragma unroll
@@ -730,13 +772,9 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     set_pair<P, D>(hb[c], 4 * mt + 2, h[c][2], h[c][3]);
                     pin_tile<P, D>(hb[c], mt);
                     if constexpr (CHAIN) {   // head reads h directly
-                        const f32x4 w0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                        const f32x4 w1h = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+                        const f32x4 w0 = ld16(tab + a.pl.head_w + 4 * mt, goff);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            l0[c] = fmaf(w0[i], h[c][i], l0[c]);
-                            l1[c] = fmaf(w1h[i], h[c][i], l1[c]);
-                        }
+                        for (int i = 0; i < 4; ++i) l0[c] = fmaf(w0[i], h[c][i], l0[c]);
                     }
                 }
             };
@@ -846,17 +884,12 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                             pin_tile<P, D>(xn[c], mt);
                         }
                     } else {
-                        const f32x4 hw0 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + g * NS + 4 * mt);
-                        const f32x4 hw1 = *reinterpret_cast<const f32x4*>(tab + a.pl.head_w + D + g * NS + 4 * mt);
+                        const f32x4 hw0 = ld16(tab + a.pl.head_w + 4 * mt, goff);
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                const float x = gelu_tail(ao[sl][c][i]);
-                                l0[c] = fmaf(hw0[i], x, l0[c]);
-                                l1[c] = fmaf(hw1[i], x, l1[c]);
-                            }
-                            pin2(l0[c], l1[c]);
+                            for (int i = 0; i < 4; ++i) l0[c] = fmaf(hw0[i], gelu_tail(ao[sl][c][i]), l0[c]);
+                            pin1(l0[c]);
                         }
                     }
                 };
@@ -875,8 +908,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                                                     a.frag + a.pl.frag[l + 1][2]};
 #pragma unroll
                             for (int m = 0; m < 3; ++m) load_a<P, D>(w1[t][m], mn[m], t, lane);
-                            const f32x4 bz = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_z[l + 1] + g * NS + 4 * t);
-                            const f32x4 bh = *reinterpret_cast<const f32x4*>(tab + a.pl.bias_h[l + 1] + g * NS + 4 * t);
+                            const f32x4 bz = ld16(tab + a.pl.bias_z[l + 1] + 4 * t, goff);
+                            const f32x4 bh = ld16(tab + a.pl.bias_h[l + 1] + 4 * t, goff);
 #pragma unroll
                             for (int c = 0; c < NTC; ++c) {
                                 s1z[t][c] = bz;
@@ -923,18 +956,17 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             for (int l = 1; l + 1 < nl; ++l) layer(F_{}, F_{}, l);
             layer(F_{}, T_{}, nl - 1);
         }
-        // head: logits = W_o x + b_o, log p of the site's own spin
-        const float bo0 = tab[a.pl.head_b], bo1 = tab[a.pl.head_b + 1];
+        // head: logits = W_o x + b_o, log p of the site's own spin; with two classes the
+        // log-softmax depends on the logit difference only
+        const float bod = tab[a.pl.head_b];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
-            float v0 = l0[c], v1 = l1[c];
-            v0 += __shfl_xor(v0, 16);
-            v1 += __shfl_xor(v1, 16);
-            v0 += __shfl_xor(v0, 32);
-            v1 += __shfl_xor(v1, 32);
-            v0 += bo0;
-            v1 += bo1;
-            const float dl = own[c] ? (v0 - v1) : (v1 - v0);
+            float v = l0[c];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            v += bod;
+            // dl = (logit of the other spin) - (logit of the own spin)
+            const float dl = own[c] ? v : -v;
             // log p = -softplus(dl) = -(max(dl, 0) + ln(1 + e^-|dl|)), in base 2 on the
             // hardware exp2/log2 (1 + e rounds to 1 only where e < 2^-24)
             const float e = __builtin_amdgcn_exp2f(fabsf(dl) * kNegLog2e);

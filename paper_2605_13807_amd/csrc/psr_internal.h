@@ -51,7 +51,7 @@ struct Prepared {
     // float offsets (in floats) into the table area
     int64_t t0z, t0h, t0d;     // layer-0 tables [9][d] in slot order (state = 3*sH + sV)
     int64_t bias_z[8], bias_h[8];   // layers >= 1: [d] in slot order
-    int64_t head_w, head_b;    // W_o [2][d] slot order, b_o [2]
+    int64_t head_w, head_b;    // W_o[0] - W_o[1] [d] slot order, b_o[0] - b_o[1]
     int64_t table_floats;
 };
 
