@@ -59,7 +59,7 @@ typedef struct {
     int32_t n_layers;   /* chain: 1 */
     int32_t d;          /* hidden size d = d_h; 32, 64, 128 or 256 */
     int32_t precision;  /* PSR_FP32 or PSR_BF16 (input type of the dense projections) */
-    int32_t ckpt_rows;  /* rows per backward checkpoint chunk; 0 = max(1, 64 / lx) */
+    int32_t ckpt_rows;  /* rows per backward checkpoint chunk; 0 = max(1, 128 / lx) */
 } psr_model_desc;
 
 /*

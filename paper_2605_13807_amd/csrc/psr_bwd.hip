@@ -100,27 +100,50 @@ struct MB { const float* p; int sk, sn; };
 struct MC { float* p; int sm, sn; };
 
 // Offsets are 32-bit element offsets from a workgroup-uniform base (every
-// operand lives in one sample's scratch, its row of O or theta), so the loads
-// take the scalar-base + 32-bit-offset form.
+// operand lives in one sample's scratch, its row of O or theta).  Operands are
+// read with buffer loads: the K step of a load is a scalar offset and the lane's
+// part one vector offset per tile, so no per-load address arithmetic reaches the
+// vector unit.  Full K blocks run unchecked; a ragged last block zeroes A beyond
+// K.  A column n >= N of B only feeds output column n, which is not stored, so
+// its address is clamped instead of masked (no branches around the loads).
+__device__ inline float ldbuf(__amdgpu_buffer_rsrc_t r, int voff_bytes, int soff_bytes) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff_bytes, soff_bytes, 0));
+}
+
 __device__ void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int tm = M >> 4, tn = (N + 15) >> 4;
     const int kq = lane >> 4, r16 = lane & 15;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.p), 0, 0x7ffffff0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(b.p), 0, 0x7ffffff0, 0x00020000);
+    const int Kf = K & ~31;   // K covered by full blocks of 32
     for (int t = wave; t < tm * tn; t += nw) {
         const int m0 = (t % tm) << 4, n0 = (t / tm) << 4;
         const int n = n0 + r16;
         const bool nok = n < N;
-        const int ao = (m0 + r16) * a.sm, bo = (nok ? n : 0) * b.sn;
+        const int av0 = ((m0 + r16) * a.sm + kq * a.sk) * 4;        // bytes, lane part
+        const int bv0 = ((nok ? n : N - 1) * b.sn + kq * b.sk) * 4;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         // K in blocks of 32: the block's 16 loads are issued together, then 8 MFMAs
-        for (int k0 = 0; k0 < K; k0 += 32) {
+        for (int k0 = 0; k0 < Kf; k0 += 32) {
             float av[8], bv[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int k = k0 + 4 * q + kq;
-                const bool kok = k < K;
-                av[q] = kok ? a.p[ao + k * a.sk] : 0.0f;
-                bv[q] = (kok && nok) ? b.p[bo + k * b.sk] : 0.0f;
+                av[q] = ldbuf(ra, av0, (k0 + 4 * q) * a.sk * 4);
+                bv[q] = ldbuf(rb, bv0, (k0 + 4 * q) * b.sk * 4);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc, 0, 0, 0);
+        }
+        if (Kf < K) {
+            // last, partial block: rows k >= K of A read as zero (their addresses clamped to K - 1)
+            float av[8], bv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = Kf + 4 * q + kq;
+                const float x = ldbuf(ra, ((m0 + r16) * a.sm + min(k, K - 1) * a.sk) * 4, 0);
+                av[q] = (k < K) ? x : 0.0f;
+                bv[q] = ldbuf(rb, ((nok ? n : N - 1) * b.sn + min(k, K - 1) * b.sk) * 4, 0);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc, 0, 0, 0);
@@ -502,7 +525,8 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
 
 BwdLayout bwd_layout(const Geom& g, int ckpt_rows) {
     BwdLayout bl;
-    int R = ckpt_rows > 0 ? ckpt_rows : (64 / g.lx > 1 ? 64 / g.lx : 1);
+    // default: about 128 sites per chunk (measured best or within 1 % of it at 10x10, 32x32, 52x52)
+    int R = ckpt_rows > 0 ? ckpt_rows : (128 / g.lx > 1 ? 128 / g.lx : 1);
     if (R > g.ly) R = g.ly;
     bl.rows_per_chunk = R;
     bl.n_chunks = (g.ly + R - 1) / R;
