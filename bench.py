@@ -104,6 +104,7 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sampler", action="store_true", help="skip the sampler measurement")
     ap.add_argument("--chunk", type=int, default=32768)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM traffic counters)")
@@ -214,6 +215,32 @@ def main() -> int:
         print(f"# fp32: {v32:.4e} site-evals/s", file=sys.stderr, flush=True)
         del r32
 
+    # exact autoregressive sampler (the step before the path), timed on its own: one
+    # kernel per call, on the current stream, bracketed by events on that stream
+    sampler = None
+    if not args.no_sampler:
+        ms_ = P.Model(P.SNAKE_2D, L, L, nl, d, prec)
+        u_ = torch.from_numpy(I.uniforms(B, N, 3000 + k)).to(dev)
+        ws_s = P._workspace(ms_, P.OP_SAMPLE, B, dev)
+        P.sample(ms_, r["th"], u_, ws=ws_s)
+        torch.cuda.synchronize()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.sample(ms_, r["th"], u_, ws=ws_s)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_call = e0.elapsed_time(e1) / reps
+        tfl = F * N * B / (ms_call / 1000.0) / 1e12
+        sampler = {"kernel": "sample_kernel", "samples": B, "ms_per_call": round(ms_call, 3),
+                   "samples_per_s": round(B / (ms_call / 1000.0), 1),
+                   "site_evals_per_s": B * N / (ms_call / 1000.0), "dtype": "f32",
+                   "bound": "mfma", "achieved": round(tfl, 2), "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s",
+                   "frac": round(tfl / PEAK["fp32_tflops"], 4)}
+        print(f"# sampler: {ms_call:.1f} ms per {B} samples", file=sys.stderr, flush=True)
+        del ws_s
+
     # CPU oracle baseline on a bounded sample, and the E_loc error on that sample
     cpu = None
     err = None
@@ -281,6 +308,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp32_path": fp32,
+        "sampler": sampler,
         "error": err,
     }
     print(json.dumps(line))

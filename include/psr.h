@@ -96,6 +96,7 @@ int64_t psr_max_connected(const psr_hamiltonian* H);
 #define PSR_OP_LOGPSI        0
 #define PSR_OP_LOCAL_ENERGY  1
 #define PSR_OP_BACKWARD      2
+#define PSR_OP_SAMPLE        3
 
 /* Device workspace bytes that `op` needs for a batch of `batch` samples
  * (`chunk_seqs` only matters for PSR_OP_LOCAL_ENERGY).  Negative on error. */
@@ -172,6 +173,23 @@ int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_
  * (2/B) sum_s (E_loc(s) - mean) O_s.   eloc, stats, w: device doubles.
  */
 int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, void* stream);
+
+/*
+ * Exact autoregressive samples (Sec. III.B: p(sigma) = prod_t p(sigma_t | sigma_<t),
+ * sites in the zigzag order of Sec. II.F): site by site, every layer of the
+ * model runs at the site on the spins drawn so far and
+ *     sigma_t = 1  iff  uniforms[b][t] < p(sigma_t = 1 | sigma_<t),
+ * with p computed in float32 (the sampler runs in FP32 whatever m->precision
+ * is).  The random numbers are the caller's: equal uniforms give equal samples.
+ * 2D snake model only (PSR_EUNSUPPORTED for the chain).
+ *   theta      device, float[P]
+ *   uniforms   device, float[B][N] in [0, 1), lattice row-major (site y * lx + x)
+ *   spins      device, int8[B][N]     (out) the samples, lattice row-major
+ *   logpsi     device, float[B]       (out) log psi of each sample (FP32 model)
+ *   ws         device workspace of psr_workspace_bytes(m, PSR_OP_SAMPLE, B, 0) bytes
+ */
+int psr_sample(const psr_model_desc* m, const float* theta, const float* uniforms, int64_t B,
+               int8_t* spins, float* logpsi, void* ws, size_t ws_bytes, void* stream);
 
 /* Synchronous check of a spin batch: PSR_OK if every value is 0 or 1, PSR_EDATA otherwise. */
 int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream);

@@ -16,6 +16,8 @@ Modules
 ``hamiltonian``  TFIM and (Marshall-rotated) Heisenberg: canonical connected
                  configurations, matrix elements, diagonal part, E_loc, dense
                  Hamiltonians from Pauli Kronecker products, exact spectra.
+``sample``       exact autoregressive sampling with given uniforms, site by
+                 site in the order of the factorisation.
 ``grad``         per-sample d log psi / d theta by float64 torch autograd on
                  the CPU (a second, separately written forward), central finite
                  differences of ``model``, and the VMC batch statistics.
@@ -24,4 +26,4 @@ Every function cites the passage of the paper it follows.  Pins (what fixes
 each function other than itself) live in ``tests/test_oracle_pins.py``.
 """
 
-from . import model, hamiltonian  # noqa: F401
+from . import model, hamiltonian, sample  # noqa: F401

@@ -27,7 +27,7 @@ __all__ = [
 CHAIN_1D, SNAKE_2D = 0, 1
 FP32, BF16 = 0, 1
 TFIM, HEISENBERG = 0, 1
-OP_LOGPSI, OP_LOCAL_ENERGY, OP_BACKWARD = 0, 1, 2
+OP_LOGPSI, OP_LOCAL_ENERGY, OP_BACKWARD, OP_SAMPLE = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsr.so")
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
         L.psr_local_energy.restype = ctypes.c_int
         L.psr_logpsi_backward.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
         L.psr_logpsi_backward.restype = ctypes.c_int
+        L.psr_sample.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp, sz, vp]
+        L.psr_sample.restype = ctypes.c_int
         L.psr_vmc_weights.argtypes = [vp, vp, i64, vp, vp]
         L.psr_vmc_weights.restype = ctypes.c_int
         L.psr_check_spins.argtypes = [vp, i64, vp]
@@ -249,6 +251,27 @@ def logpsi_backward(m: Model, theta: torch.Tensor, spins: torch.Tensor, w: torch
     _check(lib().psr_logpsi_backward(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(O), _ptr(lp), _ptr(w),
                                      _ptr(g), _ptr(ws), ws.numel(), _stream(dev)))
     return O, lp, g
+
+
+def sample(m: Model, theta: torch.Tensor, uniforms: torch.Tensor, ws: torch.Tensor | None = None):
+    """Exact autoregressive samples: (spins [B, N] int8, log psi [B] float32).
+
+    ``uniforms`` [B, N] float32 in [0, 1), lattice row-major: site t takes spin 1
+    iff its uniform is below p(sigma_t = 1 | sigma_<t).
+    """
+    theta = _dev(theta, torch.float32, "theta")
+    uniforms = _dev(uniforms, torch.float32, "uniforms")
+    B, N = uniforms.shape
+    if N != m.n_sites:
+        raise ValueError(f"uniforms has {N} sites, the model {m.n_sites}")
+    dev = uniforms.device
+    spins = torch.empty(B, N, dtype=torch.int8, device=dev)
+    lp = torch.empty(B, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = _workspace(m, OP_SAMPLE, B, dev)
+    _check(lib().psr_sample(ctypes.byref(m.c()), _ptr(theta), _ptr(uniforms), B, _ptr(spins), _ptr(lp), _ptr(ws),
+                            ws.numel(), _stream(dev)))
+    return spins, lp
 
 
 def vmc_weights(eloc: torch.Tensor, stats: torch.Tensor) -> torch.Tensor:

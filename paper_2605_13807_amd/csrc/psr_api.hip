@@ -410,6 +410,10 @@ int64_t psr_workspace_bytes(const psr_model_desc* m, int32_t op, int64_t batch, 
         BwdWs w;
         return carve_bwd(g, m->ckpt_rows, batch, true, nullptr, &w);
     }
+    if (op == PSR_OP_SAMPLE) {
+        if (g.chain) return fail(PSR_EUNSUPPORTED, "the sampler covers the 2D snake model");
+        return sample_groups(batch) * sample_ws_per_wg_floats(g) * (int64_t)sizeof(float);
+    }
     return fail(PSR_EINVAL, "unknown op %d", op);
 }
 
@@ -547,6 +551,25 @@ int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_
                        "backward")))
         return r;
     if (gout && (r = dev_check(launch_weighted_sum(Ouse, B, param_count(g), w, gout, st), "gradient sum"))) return r;
+    return ok();
+}
+
+int psr_sample(const psr_model_desc* m, const float* theta, const float* uniforms, int64_t B, int8_t* spins,
+               float* logpsi, void* ws, size_t ws_bytes, void* stream) {
+    Geom g;
+    int r = check_model(m, &g);
+    if (r) return r;
+    if (g.chain) return fail(PSR_EUNSUPPORTED, "the sampler covers the 2D snake model");
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !uniforms || !spins || !logpsi) return fail(PSR_EINVAL, "theta, uniforms, spins and logpsi must not be NULL");
+    const int64_t need = sample_groups(B) * sample_ws_per_wg_floats(g) * (int64_t)sizeof(float);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    if ((r = dev_check(launch_sample(g, theta, uniforms, B, spins, logpsi, reinterpret_cast<float*>(ws),
+                                     as_stream(stream)),
+                       "sample")))
+        return r;
     return ok();
 }
 

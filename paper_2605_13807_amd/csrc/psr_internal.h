@@ -122,6 +122,11 @@ int launch_stats(const double* x, int64_t B, double* stats, hipStream_t st);
 int launch_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, hipStream_t st);
 int launch_combine_logpsi(const float* hi, const float* lo, int64_t B, float* out, hipStream_t st);
 
+// Sampler (psr_sample.hip): workgroups of sequences, per-workgroup workspace
+int64_t sample_ws_per_wg_floats(const Geom& g);
+int64_t sample_groups(int64_t B);
+int launch_sample(const Geom& g, const float* theta, const float* u, int64_t B, int8_t* spins, float* logpsi,
+                  float* scratch, hipStream_t st);
 // Backward (psr_bwd.hip)
 struct BwdLayout {
     int rows_per_chunk, n_chunks;

@@ -28,6 +28,7 @@ __all__ = [
     "spins_bernoulli",
     "spins_zero_mag",
     "spins_neel_like",
+    "uniforms",
 ]
 
 
@@ -107,3 +108,8 @@ def spins_neel_like(batch: int, lx: int, ly: int, seed: int, n_swaps: int | None
                 done += 1
         out[b] = s
     return out
+
+
+def uniforms(batch: int, n_sites: int, seed: int) -> np.ndarray:
+    """Random numbers for the sampler: float32 [batch, n_sites] in [0, 1), one per site."""
+    return rng(seed).random((batch, n_sites), dtype=np.float32)

@@ -435,3 +435,59 @@ def test_round_bf16_matches_library_conversion():
     ]).astype(np.float32)
     want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(M.round_bf16(x), want)
+
+
+# ----------------------------------------------------------------------------
+# f1: exact autoregressive sampling (Sec. III.B) against the brute-force distribution
+# ----------------------------------------------------------------------------
+
+def _chi2_pvalue(samples: np.ndarray, p: np.ndarray) -> float:
+    """Pearson chi^2 of sampled configuration counts against p (bins with expected < 5 merged)."""
+    from scipy.stats import chi2
+
+    n = samples.shape[1]
+    idx = (samples.astype(np.int64) * (1 << np.arange(n - 1, -1, -1))).sum(axis=1)   # all_configs order
+    counts = np.bincount(idx, minlength=1 << n).astype(np.float64)
+    expected = p * samples.shape[0]
+    big = expected >= 5
+    obs = np.append(counts[big], counts[~big].sum())
+    exp_ = np.append(expected[big], expected[~big].sum())
+    keep = exp_ > 0
+    stat = float(((obs[keep] - exp_[keep]) ** 2 / exp_[keep]).sum())
+    return float(chi2.sf(stat, keep.sum() - 1))
+
+
+@pytest.mark.parametrize("geom,lx,ly,nl,d", [("snake2d", 3, 3, 2, 32), ("snake2d", 4, 2, 3, 32), ("chain", 8, 1, 1, 32)])
+def test_f1_sampler_reproduces_brute_force_distribution(geom, lx, ly, nl, d):
+    from oracle import sample as S
+
+    m = M.Model(geom, lx, ly, nl, d)
+    th = 1.5 * I.params(M.n_params(m), d, 77)          # far from uniform, mass spread over many bins
+    N = lx * ly
+    p = np.exp(2.0 * M.logpsi(th, M.all_configs(N), m))
+    assert abs(math.fsum(p) - 1.0) < 1e-12
+    u = I.rng(78).random((40000, N))
+    s, lp = S.sample(th, u, m)
+    assert np.allclose(lp, M.logpsi(th, s, m), atol=1e-12)
+    pv = _chi2_pvalue(s, p)
+    assert pv > 1e-3, pv
+    # planted mistake: the two classes swapped (sigma_t = 1 iff u < 1 - p) must be rejected
+    wrong = np.zeros_like(s)
+    for t in S.visiting_order(m):
+        wrong[:, t] = (u[:, t] < 1.0 - S.conditionals(th, wrong, m)[:, t]).astype(np.int8)
+    assert _chi2_pvalue(wrong, p) < 1e-6
+
+
+def test_f1_sampler_decision_rule():
+    from oracle import sample as S
+
+    m = M.Model("snake2d", 3, 2, 2, 32)
+    th = I.params(M.n_params(m), 32, 79)
+    s0, _ = S.sample(th, np.zeros((2, 6)), m)               # u = 0 < p: every spin 1
+    s1, _ = S.sample(th, np.ones((2, 6)), m)                # u = 1 >= p: every spin 0
+    assert (s0 == 1).all() and (s1 == 0).all()
+    # the conditionals of a sample are those its decisions were taken on
+    u = I.rng(80).random((16, 6))
+    s, _ = S.sample(th, u, m)
+    p1 = S.conditionals(th, s, m)
+    assert ((u < p1) == (s == 1)).all()
