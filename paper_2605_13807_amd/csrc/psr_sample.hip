@@ -9,7 +9,7 @@
 // (no scan): h = z h_H + (1 - z) htilde with h_H the previous site of the row
 // (zero at a row start) and h_V the row above (zero on the first row).
 //
-// One workgroup draws kS sequences.  Per site and layer the dense products are
+// One workgroup (8 waves) draws kS sequences.  Per site and layer the dense products are
 // FP32 MFMA GEMMs with the kS sequences as the N dimension (psr_gemm.h), over
 // the workgroup's workspace: the row frontier FR[l][i] (h^(l) of the row above
 // at column i), the horizontal state HH[l], and the activations X, Z, HT, PRE
@@ -29,7 +29,9 @@ namespace {
 using namespace gemm_detail;
 
 constexpr int kS = 16;          // sequences per workgroup (the GEMM N dimension)
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;      // 8 waves: one 16-unit output tile each at d = 128
+constexpr int kLanesPerSeq = kThreads / kS;   // head: threads per sequence (a power of two <= 64)
+static_assert(kLanesPerSeq <= 64 && (kLanesPerSeq & (kLanesPerSeq - 1)) == 0, "head lanes per sequence");
 
 struct SampleArgs {
     Geom g;
@@ -141,20 +143,20 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
                 for (int e = tid; e < DS; e += kThreads) X[e] = gelu(PRE[e]);
                 __syncthreads();
             }
-            // ---- head: logits = W_o x + b_o; 16 threads per sequence
+            // ---- head: logits = W_o x + b_o; kLanesPerSeq threads per sequence
             {
-                const int n = tid >> 4, r = tid & 15;
+                const int n = tid / kLanesPerSeq, r = tid % kLanesPerSeq;
                 const int64_t oWo = a.off[6 * nl], obo = a.off[6 * nl + 1];
                 float l0 = 0.0f, l1 = 0.0f;
-                for (int m = r; m < d; m += 16) {
+                for (int m = r; m < d; m += kLanesPerSeq) {
                     const float x = X[m * kS + n];
                     l0 = fmaf(th[oWo + m], x, l0);
                     l1 = fmaf(th[oWo + d + m], x, l1);
                 }
 #pragma unroll
-                for (int w = 8; w >= 1; w >>= 1) {
-                    l0 += __shfl_xor(l0, w, 16);
-                    l1 += __shfl_xor(l1, w, 16);
+                for (int w = kLanesPerSeq / 2; w >= 1; w >>= 1) {
+                    l0 += __shfl_xor(l0, w, kLanesPerSeq);
+                    l1 += __shfl_xor(l1, w, kLanesPerSeq);
                 }
                 if (r == 0) {
                     const float dl = (l0 + th[obo]) - (l1 + th[obo + 1]);   // logit(0) - logit(1)
