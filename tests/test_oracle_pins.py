@@ -466,7 +466,7 @@ def test_f1_sampler_reproduces_brute_force_distribution(geom, lx, ly, nl, d):
     N = lx * ly
     p = np.exp(2.0 * M.logpsi(th, M.all_configs(N), m))
     assert abs(math.fsum(p) - 1.0) < 1e-12
-    u = I.rng(78).random((40000, N))
+    u = I.rng(78).random((20000, N))
     s, lp = S.sample(th, u, m)
     assert np.allclose(lp, M.logpsi(th, s, m), atol=1e-12)
     pv = _chi2_pvalue(s, p)
