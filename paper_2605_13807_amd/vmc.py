@@ -1,0 +1,64 @@
+"""Single-GPU variational Monte Carlo on top of the library (the training step of Sec. III.B).
+
+One step: draw exact samples from |psi|^2 (``sample``), evaluate their local
+energies and FP64 statistics (``local_energy``), turn them into the weights of
+the energy-gradient estimator g = (2/B) sum_s (E_loc(s) - mean) d log psi(s) / d theta
+(``vmc_weights``, real positive psi), get g from the per-sample backward
+(``logpsi_backward``) and update theta with Adam.  Every model evaluation runs
+in the HIP library; this module only strings the calls together and keeps the
+optimiser state (PyTorch tensors on the same device).
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import (OP_BACKWARD, OP_LOCAL_ENERGY, OP_SAMPLE, Hamiltonian, Model, _workspace, local_energy,
+               logpsi_backward, sample, vmc_weights)
+
+
+class Adam:
+    """Adam (Kingma and Ba) on a flat parameter vector: m, v moments, bias-corrected step."""
+
+    def __init__(self, n: int, device, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.lr, (self.b1, self.b2), self.eps = lr, betas, eps
+        self.m = torch.zeros(n, dtype=torch.float64, device=device)
+        self.v = torch.zeros(n, dtype=torch.float64, device=device)
+        self.t = 0
+
+    def step(self, theta: torch.Tensor, g: torch.Tensor) -> None:
+        self.t += 1
+        self.m.mul_(self.b1).add_(g, alpha=1.0 - self.b1)
+        self.v.mul_(self.b2).addcmul_(g, g, value=1.0 - self.b2)
+        mh = self.m / (1.0 - self.b1 ** self.t)
+        vh = self.v / (1.0 - self.b2 ** self.t)
+        theta.sub_((self.lr * mh / (vh.sqrt() + self.eps)).to(theta.dtype))
+
+
+def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, lr: float = 1e-3, seed: int = 0,
+        log_every: int = 0):
+    """Run `steps` VMC steps in place on `theta` (float32, device).  Returns [(mean E, variance)] per step.
+
+    The uniforms of the sampler come from a seeded torch generator on the
+    device, so a run is reproducible for a given seed.
+    """
+    dev = theta.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    opt = Adam(theta.numel(), dev, lr=lr)
+    ws_s = _workspace(m, OP_SAMPLE, batch, dev)
+    ws_e = _workspace(m, OP_LOCAL_ENERGY, batch, dev)
+    ws_b = _workspace(m, OP_BACKWARD, batch, dev)
+    hist = []
+    for k in range(steps):
+        u = torch.rand(batch, m.n_sites, generator=gen, device=dev, dtype=torch.float32)
+        spins, _ = sample(m, theta, u, ws=ws_s)
+        e, st, _ = local_energy(m, theta, h, spins, ws=ws_e)
+        w = vmc_weights(e, st)
+        _, _, g = logpsi_backward(m, theta, spins, w=w, want_O=False, ws=ws_b)
+        opt.step(theta, g)
+        mean, var = (float(x) for x in st.cpu())
+        hist.append((mean, var))
+        if log_every and (k + 1) % log_every == 0:
+            print(f"  step {k + 1}: E = {mean:.6f}, var = {var:.3e}", flush=True)
+    return hist

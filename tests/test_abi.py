@@ -128,3 +128,23 @@ def test_workspace_sizes_grow_with_batch(P):
         a = P.workspace_bytes(m, op, 100, 1000)
         b = P.workspace_bytes(m, op, 200, 1000)
         assert 0 < a < b
+
+
+def test_vmc_adam_matches_torch_adam():
+    """The VMC loop's Adam step against torch.optim.Adam on the same gradients (CPU)."""
+    import torch
+
+    from paper_2605_13807_amd.vmc import Adam
+
+    g = torch.Generator().manual_seed(0)
+    th = torch.randn(50, generator=g)
+    ref = th.clone().double().requires_grad_(True)
+    opt_ref = torch.optim.Adam([ref], lr=1e-2)
+    opt = Adam(50, "cpu", lr=1e-2)
+    mine = th.clone().double()
+    for _ in range(5):
+        grad = torch.randn(50, generator=g, dtype=torch.float64)
+        ref.grad = grad.clone()
+        opt_ref.step()
+        opt.step(mine, grad)
+    assert torch.allclose(mine, ref.detach(), rtol=0, atol=1e-12)
