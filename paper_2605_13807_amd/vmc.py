@@ -11,6 +11,8 @@ optimiser state (PyTorch tensors on the same device).
 
 from __future__ import annotations
 
+import math
+
 import torch
 
 from . import (OP_BACKWARD, OP_LOCAL_ENERGY, OP_SAMPLE, Hamiltonian, Model, _workspace, local_energy,
@@ -35,17 +37,30 @@ class Adam:
         theta.sub_((self.lr * mh / (vh.sqrt() + self.eps)).to(theta.dtype))
 
 
-def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, lr: float = 1e-3, seed: int = 0,
+def lr_decay(eta0: float, delta0: float):
+    """Learning-rate decay of the paper's training appendix: eta(t) = eta0 / (1 + t / delta0)."""
+    return lambda t: eta0 / (1.0 + t / delta0)
+
+
+def n_steps(L: int, s: float, C: float, r: float, L0: int, F: float) -> int:
+    """Training steps for iterative retraining at linear size L (training appendix):
+    ceil(s (C exp(-r (L - L0)) + F))."""
+    return int(math.ceil(s * (C * math.exp(-r * (L - L0)) + F)))
+
+
+def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, lr=1e-3, seed: int = 0,
         log_every: int = 0):
     """Run `steps` VMC steps in place on `theta` (float32, device).  Returns [(mean E, variance)] per step.
 
-    The uniforms of the sampler come from a seeded torch generator on the
-    device, so a run is reproducible for a given seed.
+    ``lr`` is a constant or a function of the step index t = 0, 1, ... (e.g.
+    ``lr_decay(eta0, delta0)``).  The uniforms of the sampler come from a seeded
+    torch generator on the device, so a run is reproducible for a given seed.
     """
     dev = theta.device
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
-    opt = Adam(theta.numel(), dev, lr=lr)
+    sched = lr if callable(lr) else (lambda t: lr)
+    opt = Adam(theta.numel(), dev, lr=sched(0))
     ws_s = _workspace(m, OP_SAMPLE, batch, dev)
     ws_e = _workspace(m, OP_LOCAL_ENERGY, batch, dev)
     ws_b = _workspace(m, OP_BACKWARD, batch, dev)
@@ -56,6 +71,7 @@ def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, l
         e, st, _ = local_energy(m, theta, h, spins, ws=ws_e)
         w = vmc_weights(e, st)
         _, _, g = logpsi_backward(m, theta, spins, w=w, want_O=False, ws=ws_b)
+        opt.lr = sched(k)
         opt.step(theta, g)
         mean, var = (float(x) for x in st.cpu())
         hist.append((mean, var))

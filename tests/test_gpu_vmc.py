@@ -26,9 +26,9 @@ def P():
     return P
 
 
-@pytest.mark.parametrize("lx,ly,hfield,steps", [(12, 1, 1.0, 1500), (4, 4, 3.0, 1500)])
-def test_vmc_reaches_exact_ground_energy(P, lx, ly, hfield, steps):
-    from paper_2605_13807_amd.vmc import vmc
+@pytest.mark.parametrize("lx,ly,hfield,steps,delta0", [(12, 1, 1.0, 1500, None), (4, 4, 3.0, 1500, 500.0)])
+def test_vmc_reaches_exact_ground_energy(P, lx, ly, hfield, steps, delta0):
+    from paper_2605_13807_amd.vmc import lr_decay, vmc
 
     if ly == 1:
         exact = lx * OH.tfim_obc_exact_energy_per_site(lx)
@@ -38,7 +38,9 @@ def test_vmc_reaches_exact_ground_energy(P, lx, ly, hfield, steps):
     m = P.Model(P.SNAKE_2D, lx, ly, 2, 32, P.FP32)
     th = torch.from_numpy(I.params(P.param_count(m), 32, 1200 + lx)).cuda()
     h = P.Hamiltonian(P.TFIM, lx, ly, J=1.0, h=hfield)
-    hist = vmc(m, h, th, steps=steps, batch=1024, lr=1e-2, seed=3, log_every=250)
+    # constant learning rate, or the appendix's decay eta0 / (1 + t / delta0)
+    lr = 1e-2 if delta0 is None else lr_decay(1e-2, delta0)
+    hist = vmc(m, h, th, steps=steps, batch=1024, lr=lr, seed=3, log_every=250)
     e0 = hist[0][0]
     e = np.mean([x for x, _ in hist[-100:]])
     var = np.mean([v for _, v in hist[-100:]])
