@@ -181,7 +181,7 @@ int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* 
  *     sigma_t = 1  iff  uniforms[b][t] < p(sigma_t = 1 | sigma_<t),
  * with p computed in float32 (the sampler runs in FP32 whatever m->precision
  * is).  The random numbers are the caller's: equal uniforms give equal samples.
- * 2D snake model only (PSR_EUNSUPPORTED for the chain).
+ * Both geometries (the chain visits its sites left to right).
  *   theta      device, float[P]
  *   uniforms   device, float[B][N] in [0, 1), lattice row-major (site y * lx + x)
  *   spins      device, int8[B][N]     (out) the samples, lattice row-major

@@ -411,7 +411,6 @@ int64_t psr_workspace_bytes(const psr_model_desc* m, int32_t op, int64_t batch, 
         return carve_bwd(g, m->ckpt_rows, batch, true, nullptr, &w);
     }
     if (op == PSR_OP_SAMPLE) {
-        if (g.chain) return fail(PSR_EUNSUPPORTED, "the sampler covers the 2D snake model");
         return sample_groups(batch) * sample_ws_per_wg_floats(g) * (int64_t)sizeof(float);
     }
     return fail(PSR_EINVAL, "unknown op %d", op);
@@ -559,7 +558,6 @@ int psr_sample(const psr_model_desc* m, const float* theta, const float* uniform
     Geom g;
     int r = check_model(m, &g);
     if (r) return r;
-    if (g.chain) return fail(PSR_EUNSUPPORTED, "the sampler covers the 2D snake model");
     if (B < 0) return fail(PSR_EINVAL, "negative batch");
     if (B == 0) return ok();
     if (!theta || !uniforms || !spins || !logpsi) return fail(PSR_EINVAL, "theta, uniforms, spins and logpsi must not be NULL");

@@ -1,4 +1,4 @@
-// Exact autoregressive sampling of the 2D snake model in step mode.
+// Exact autoregressive sampling of the 2D snake model and the chain, in step mode.
 //
 // The model is autoregressive (Sec. III.B): p(sigma) = prod_t p(sigma_t | sigma_<t)
 // along the snake order of Sec. II.F, so an exact sample is drawn site by site:
@@ -15,7 +15,9 @@
 // at column i), the horizontal state HH[l], and the activations X, Z, HT, PRE
 // ([d][kS] each, unit-major).  The sampled spins of the current and the
 // previous row stay in LDS.  Everything runs in FP32, whatever the model's
-// precision.
+// precision.  The chain (one layer, input the one-hot previous spin, head on h)
+// takes the same path with a one-site-high lattice, no vertical input and no
+// output block.
 
 #include <hip/hip_runtime.h>
 
@@ -78,8 +80,21 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
             const int ih = (j & 1) ? i + 1 : i - 1;     // horizontal predecessor
             const bool hp = t > 0, vp = j > 0;
             // ---- layer 0: u is (one-hot spin at H-pred, one-hot spin at V-pred), so its
-            //      products are column gathers
-            {
+            //      products are column gathers (chain: the one-hot previous spin only)
+            if (G.chain) {
+                const int64_t oWz = a.off[0], obz = a.off[1], oWh = a.off[2], obh = a.off[3];
+                for (int e = tid; e < DS; e += kThreads) {
+                    const int m = e / kS, n = e % kS;
+                    float cz = th[obz + m], ch = th[obh + m];
+                    if (hp) {
+                        const int c = spc[ih * kS + n];
+                        cz += th[oWz + m * 2 + c];
+                        ch += th[oWh + m * 2 + c];
+                    }
+                    Z[e] = cz;
+                    HT[e] = ch;
+                }
+            } else {
                 const int64_t oWz = a.off[0], obz = a.off[1], oWh = a.off[2], obh = a.off[3], oD = a.off[5];
                 for (int e = tid; e < DS; e += kThreads) {
                     const int m = e / kS, n = e % kS;
@@ -137,6 +152,7 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
                     fr[e] = h;
                 }
                 __syncthreads();
+                if (G.chain) break;   // one layer; the head reads h
                 // x^(l+1) = GELU(C h + D u + s)
                 gemm(d, kS, d, MA{th + oC, d, 1}, MB{hh, kS, 1}, MC{PRE, kS, 1}, true);
                 __syncthreads();
@@ -146,10 +162,12 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
             // ---- head: logits = W_o x + b_o; kLanesPerSeq threads per sequence
             {
                 const int n = tid / kLanesPerSeq, r = tid % kLanesPerSeq;
-                const int64_t oWo = a.off[6 * nl], obo = a.off[6 * nl + 1];
+                const int ih0 = G.chain ? 4 : 6 * nl;   // index of W_o in the tensor list
+                const int64_t oWo = a.off[ih0], obo = a.off[ih0 + 1];
+                const float* xo = G.chain ? HH : X;    // chain: the head reads h
                 float l0 = 0.0f, l1 = 0.0f;
                 for (int m = r; m < d; m += kLanesPerSeq) {
-                    const float x = X[m * kS + n];
+                    const float x = xo[m * kS + n];
                     l0 = fmaf(th[oWo + m], x, l0);
                     l1 = fmaf(th[oWo + d + m], x, l1);
                 }

@@ -6,7 +6,7 @@ sigma_<t).  The kernel takes that decision on its float32 p, the oracle's p is
 float64, so a disagreement is accepted only where u_t lies within the float32
 error of p (|u_t - p| <= 2e-5).  log psi of each sample: the FP32 bar of
 test_gpu_parity.py.  The distribution: Pearson chi^2 of 40000 GPU samples
-against the brute-force p of a 3x3 model.
+against the brute-force p of a 3x3 model.  Both geometries (snake and chain).
 """
 
 import numpy as np
@@ -31,23 +31,25 @@ def P():
 
 
 SAMPLE_CASES = [
-    # lx, ly, nl, d, prec, B, theta scale
-    (4, 4, 3, 32, 0, 37, 1.5),      # residual active, ragged workgroup, uneven conditionals
-    (5, 3, 2, 64, 0, 50, 1.0),      # odd width
-    (1, 6, 2, 32, 1, 20, 1.5),      # one column; BF16 model descriptor (the sampler is FP32)
-    (7, 1, 2, 32, 0, 16, 1.5),      # one row
-    (10, 10, 2, 64, 0, 40, 1.0),    # the 10x10 workload shape
-    (6, 5, 3, 128, 0, 20, 1.5),
-    (3, 4, 4, 256, 0, 17, 1.0),
-    (32, 32, 3, 128, 1, 32, 1.0),   # the 32x32 workload shape
+    # geometry (0 chain, 1 snake), lx, ly, nl, d, prec, B, theta scale
+    (1, 4, 4, 3, 32, 0, 37, 1.5),      # residual active, ragged workgroup, uneven conditionals
+    (1, 5, 3, 2, 64, 0, 50, 1.0),      # odd width
+    (1, 1, 6, 2, 32, 1, 20, 1.5),      # one column; BF16 model descriptor (the sampler is FP32)
+    (1, 7, 1, 2, 32, 0, 16, 1.5),      # one row
+    (1, 10, 10, 2, 64, 0, 40, 1.0),    # the 10x10 workload shape
+    (1, 6, 5, 3, 128, 0, 20, 1.5),
+    (1, 3, 4, 4, 256, 0, 17, 1.0),
+    (1, 32, 32, 3, 128, 1, 32, 1.0),   # the 32x32 workload shape
+    (0, 16, 1, 1, 32, 0, 40, 1.5),     # the 16-site chain workload
+    (0, 9, 1, 1, 64, 0, 19, 2.0),
 ]
 
 
-@pytest.mark.parametrize("lx,ly,nl,d,prec,B,scale", SAMPLE_CASES)
-def test_sample_decisions_and_logpsi(P, lx, ly, nl, d, prec, B, scale):
-    print(f"sample case {lx}x{ly} nl={nl} d={d} prec={prec} B={B} scale={scale}", flush=True)
-    m = P.Model(P.SNAKE_2D, lx, ly, nl, d, prec)
-    om = OM.Model("snake2d", lx, ly, nl, d)
+@pytest.mark.parametrize("geom,lx,ly,nl,d,prec,B,scale", SAMPLE_CASES)
+def test_sample_decisions_and_logpsi(P, geom, lx, ly, nl, d, prec, B, scale):
+    print(f"sample case geom={geom} {lx}x{ly} nl={nl} d={d} prec={prec} B={B} scale={scale}", flush=True)
+    m = P.Model(geom, lx, ly, nl, d, prec)
+    om = OM.Model("chain" if geom == 0 else "snake2d", lx, ly, nl, d)
     th = (scale * I.params(OM.n_params(om), d, 300 + lx)).astype(np.float32)
     u = I.uniforms(B, lx * ly, 400 + lx)
     s, lp = P.sample(m, torch.from_numpy(th).cuda(), torch.from_numpy(u).cuda())
@@ -102,9 +104,8 @@ def test_sample_agrees_with_logpsi_and_edges(P):
     ones, _ = P.sample(m, th, torch.zeros_like(u))
     zeros, _ = P.sample(m, th, torch.ones_like(u))
     assert bool((ones == 1).all()) and bool((zeros == 0).all())
-    # empty batch, and the chain model (not covered by the sampler)
+    # empty batch; uniforms of the wrong width
     e, le = P.sample(m, th, u[:0])
     assert e.shape == (0, 24) and le.numel() == 0
-    chain = P.Model(P.CHAIN_1D, 16, 1, 1, 32, 0)
-    with pytest.raises(P.PsrError):
-        P.sample(chain, torch.from_numpy(I.params(P.param_count(chain), 32, 92)).cuda(), torch.zeros(2, 16).cuda())
+    with pytest.raises(ValueError):
+        P.sample(m, th, torch.zeros(2, 23).cuda())

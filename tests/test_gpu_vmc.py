@@ -2,8 +2,8 @@
 
 The loop runs the library's sampler, local energy and per-sample backward;
 training must reach the exact ground energy: the open TFIM chain at h = J = 1
-(the exact formula of Table I's caption; the 2D snake model on a 12 x 1 lattice
-is an autoregressive model of the chain) and the 4 x 4 open TFIM at h = 3
+(the exact formula of Table I's caption), with the chain model and with the 2D
+snake model on a 12 x 1 lattice (also an autoregressive model of the chain), and the 4 x 4 open TFIM at h = 3
 (exact diagonalisation).  A wrong sign or scale anywhere in the sampler, E_loc
 or the gradient would stop the energy short of the ground state.
 """
@@ -26,8 +26,12 @@ def P():
     return P
 
 
-@pytest.mark.parametrize("lx,ly,hfield,steps,delta0", [(12, 1, 1.0, 1500, None), (4, 4, 3.0, 1500, 500.0)])
-def test_vmc_reaches_exact_ground_energy(P, lx, ly, hfield, steps, delta0):
+@pytest.mark.parametrize("geom,lx,ly,hfield,steps,delta0", [
+    (1, 12, 1, 1.0, 1500, None),     # 2D snake model on a 12 x 1 lattice
+    (0, 12, 1, 1.0, 1500, None),     # the chain model (one minGRU layer, head on h)
+    (1, 4, 4, 3.0, 1500, 500.0),     # 4 x 4, with the appendix's learning-rate decay
+])
+def test_vmc_reaches_exact_ground_energy(P, geom, lx, ly, hfield, steps, delta0):
     from paper_2605_13807_amd.vmc import lr_decay, vmc
 
     if ly == 1:
@@ -35,7 +39,7 @@ def test_vmc_reaches_exact_ground_energy(P, lx, ly, hfield, steps, delta0):
     else:
         exact = OH.ground_energy(OH.Hamiltonian("tfim", lx, ly, J=1.0, h=hfield))
     print(f"VMC TFIM {lx}x{ly} h={hfield}: exact ground energy {exact:.6f}", flush=True)
-    m = P.Model(P.SNAKE_2D, lx, ly, 2, 32, P.FP32)
+    m = P.Model(geom, lx, ly, 1 if geom == 0 else 2, 32, P.FP32)
     th = torch.from_numpy(I.params(P.param_count(m), 32, 1200 + lx)).cuda()
     h = P.Hamiltonian(P.TFIM, lx, ly, J=1.0, h=hfield)
     # constant learning rate, or the appendix's decay eta0 / (1 + t / delta0)
