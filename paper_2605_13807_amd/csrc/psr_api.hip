@@ -290,8 +290,9 @@ static void timing_before(hipStream_t st, hipEvent_t* stop) {
         }
         g_tm.ev.emplace_back(a, b);
     }
-    auto& p = g_tm.ev[g_tm.used++];
-    hipEventRecord(p.first, st);
+    auto& p = g_tm.ev[g_tm.used];
+    if (hipEventRecord(p.first, st) != hipSuccess) return;   // this launch goes untimed
+    ++g_tm.used;
     *stop = p.second;
 }
 
@@ -317,7 +318,10 @@ static int run_forward(const Geom& g, const Prepared& pl, const uint32_t* packed
     hipEvent_t stop;
     timing_before(st, &stop);
     const int e = launch_forward(a, st);
-    if (stop) hipEventRecord(stop, st);
+    if (stop && hipEventRecord(stop, st) != hipSuccess) {
+        // the start event of this pair is recorded but not the stop: drop the pair
+        --g_tm.used;
+    }
     return e;
 }
 

@@ -45,7 +45,8 @@ __global__ void check_kernel(const int8_t* __restrict__ s, int64_t n, int* bad) 
 }
 
 int launch_check_spins(const int8_t* spins, int64_t n, int* bad, hipStream_t st) {
-    hipMemsetAsync(bad, 0, sizeof(int), st);
+    const hipError_t me = hipMemsetAsync(bad, 0, sizeof(int), st);
+    if (me != hipSuccess) return (int)me;
     if (n > 0) check_kernel<<<1024, 256, 0, st>>>(spins, n, bad);
     return (int)hipGetLastError();
 }
