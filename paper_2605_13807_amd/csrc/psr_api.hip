@@ -285,7 +285,7 @@ static void timing_before(hipStream_t st, hipEvent_t* stop) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess) return;
         if (hipEventCreate(&b) != hipSuccess) {
-            hipEventDestroy(a);
+            (void)hipEventDestroy(a);   // cleanup; the launch goes untimed
             return;
         }
         g_tm.ev.emplace_back(a, b);
@@ -596,7 +596,7 @@ int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream) {
     r = dev_check(launch_check_spins(spins, n_values, bad, st), "check");
     if (!r) r = dev_check((int)hipMemcpyAsync(&host, bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
     if (!r) r = dev_check((int)hipStreamSynchronize(st), "synchronise");
-    hipFree(bad);
+    (void)hipFree(bad);   // cleanup; the status that matters is r
     if (r) return r;
     if (host) return fail(PSR_EDATA, "spins outside {0, 1}");
     return ok();
