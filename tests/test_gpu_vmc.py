@@ -54,3 +54,33 @@ def test_vmc_reaches_exact_ground_energy(P, geom, lx, ly, hfield, steps, delta0)
     # variational: the mean energy does not fall below the ground energy (beyond noise)
     assert e >= exact - 5e-4 * abs(exact)
     assert var < hist[0][1]
+
+
+def test_vmc_table_one_small_chains(P):
+    """Table I's small open TFIM chains at h = 1: energy per site against the exact formula.
+
+    The paper's rows use its 1D LRU ansatz; here the 2-layer d = 32 minGRU snake
+    model on an N x 1 lattice, 1500 steps of 1024 samples with the appendix's
+    learning-rate decay.  Prints e(N), the exact value, the relative error and
+    the time per training step.
+    """
+    import time
+
+    from paper_2605_13807_amd.vmc import lr_decay, vmc
+
+    print("   N   e_vmc(N)      e_exact(N)    rel err    ms/step", flush=True)
+    for n in (6, 8, 10, 16):
+        exact = OH.tfim_obc_exact_energy_per_site(n)
+        m = P.Model(P.SNAKE_2D, n, 1, 2, 32, P.FP32)
+        th = torch.from_numpy(I.params(P.param_count(m), 32, 1300 + n)).cuda()
+        h = P.Hamiltonian(P.TFIM, n, 1, J=1.0, h=1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = vmc(m, h, th, steps=1500, batch=1024, lr=lr_decay(1e-2, 500.0), seed=5)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / 1500
+        e = np.mean([x for x, _ in hist[-100:]]) / n
+        rel = abs(e - exact) / abs(exact)
+        print(f"  {n:3d}  {e:.7f}  {exact:.7f}  {rel:.2e}  {ms:.2f}", flush=True)
+        assert rel <= 1e-3
+        assert e >= exact - 5e-4 * abs(exact)
