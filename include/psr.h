@@ -175,6 +175,16 @@ int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_
 int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, void* stream);
 
 /*
+ * The energy-gradient estimate (Sec. III.B) from per-sample gradient rows that
+ * psr_logpsi_backward returned earlier: g[p] = sum_s w[s] O[s][p], summed in
+ * FP64 in the same order as the fused path of psr_logpsi_backward (equal
+ * results).  It lets O be computed before the weights are known, e.g. on a
+ * second stream while psr_local_energy runs.
+ *   O   device float[B][P]    w   device double[B]    g   device double[P] (out)
+ */
+int psr_gradient_estimate(const float* O, int64_t B, int64_t P, const double* w, double* g, void* stream);
+
+/*
  * Exact autoregressive samples (Sec. III.B: p(sigma) = prod_t p(sigma_t | sigma_<t),
  * sites in the zigzag order of Sec. II.F): site by site, every layer of the
  * model runs at the site on the spins drawn so far and

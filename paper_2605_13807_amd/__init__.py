@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
         L.psr_logpsi_backward.restype = ctypes.c_int
         L.psr_sample.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp, sz, vp]
         L.psr_sample.restype = ctypes.c_int
+        L.psr_gradient_estimate.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.psr_gradient_estimate.restype = ctypes.c_int
         L.psr_vmc_weights.argtypes = [vp, vp, i64, vp, vp]
         L.psr_vmc_weights.restype = ctypes.c_int
         L.psr_check_spins.argtypes = [vp, i64, vp]
@@ -272,6 +274,18 @@ def sample(m: Model, theta: torch.Tensor, uniforms: torch.Tensor, ws: torch.Tens
     _check(lib().psr_sample(ctypes.byref(m.c()), _ptr(theta), _ptr(uniforms), B, _ptr(spins), _ptr(lp), _ptr(ws),
                             ws.numel(), _stream(dev)))
     return spins, lp
+
+
+def gradient_estimate(O: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+    """g = sum_s w_s O_s (float64 [P]) from per-sample rows O [B, P] (float32) and weights w [B] (float64)."""
+    O = _dev(O, torch.float32, "O")
+    w = _dev(w, torch.float64, "w")
+    B, Pn = O.shape
+    if w.shape != (B,):
+        raise ValueError("w must be [B]")
+    g = torch.empty(Pn, dtype=torch.float64, device=O.device)
+    _check(lib().psr_gradient_estimate(_ptr(O), B, Pn, _ptr(w), _ptr(g), _stream(O.device)))
+    return g
 
 
 def vmc_weights(eloc: torch.Tensor, stats: torch.Tensor) -> torch.Tensor:

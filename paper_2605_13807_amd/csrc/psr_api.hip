@@ -575,6 +575,16 @@ int psr_sample(const psr_model_desc* m, const float* theta, const float* uniform
     return ok();
 }
 
+int psr_gradient_estimate(const float* O, int64_t B, int64_t P, const double* w, double* g, void* stream) {
+    if (B < 0 || P < 0) return fail(PSR_EINVAL, "negative size");
+    if (P == 0) return ok();
+    if (!g) return fail(PSR_EINVAL, "g must not be NULL");
+    if (B > 0 && (!O || !w)) return fail(PSR_EINVAL, "O and w must not be NULL");
+    int r;
+    if ((r = dev_check(launch_weighted_sum(O, B, P, w, g, as_stream(stream)), "gradient sum"))) return r;
+    return ok();
+}
+
 int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, void* stream) {
     if (B < 0) return fail(PSR_EINVAL, "negative batch");
     if (B == 0) return ok();

@@ -279,6 +279,16 @@ def test_gradient_estimator(P):
     e, st, _ = P.local_energy(m, tt, P.Hamiltonian(1, 4, 4), ss)
     w = P.vmc_weights(e, st)
     _, _, g = P.logpsi_backward(m, tt, ss, w=w, want_O=False)
+    # the same estimate from O rows computed before the weights (on another stream)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        O, _, _ = P.logpsi_backward(m, tt, ss)
+    torch.cuda.current_stream().wait_stream(side)
+    O.record_stream(torch.cuda.current_stream())
+    g2 = P.gradient_estimate(O, w)
+    assert torch.equal(g, g2)
+    assert P.gradient_estimate(O[:0], w[:0]).abs().max().item() == 0.0
     g = g.cpu().numpy()
     assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
 
