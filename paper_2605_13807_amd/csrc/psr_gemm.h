@@ -76,5 +76,40 @@ __device__ inline void gemm(int M, int N, int K, MA a, MB b, MC c, bool acc_in) 
     }
 }
 
+// gemm() with B read by plain loads, for a B operand in LDS (buffer descriptors
+// address global memory only); K must be a multiple of 32.  C goes through
+// plain stores, so it may be in LDS as well.
+__device__ inline void gemm_lds_b(int M, int N, int K, MA a, MB b, MC c, bool acc_in) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int tm = M >> 4, tn = (N + 15) >> 4;
+    const int kq = lane >> 4, r16 = lane & 15;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.p), 0, 0x7ffffff0, 0x00020000);
+    for (int t = wave; t < tm * tn; t += nw) {
+        const int m0 = (t % tm) << 4, n0 = (t / tm) << 4;
+        const int n = n0 + r16;
+        const bool nok = n < N;
+        const int av0 = ((m0 + r16) * a.sm + kq * a.sk) * 4;
+        const float* bp = b.p + (nok ? n : N - 1) * b.sn + kq * b.sk;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            float av[8], bv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                av[q] = ldbuf(ra, av0, (k0 + 4 * q) * a.sk * 4);
+                bv[q] = bp[(k0 + 4 * q) * b.sk];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc, 0, 0, 0);
+        }
+        if (nok) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float* cp = c.p + ((m0 + 4 * kq + i) * c.sm + n * c.sn);
+                *cp = acc_in ? *cp + acc[i] : acc[i];
+            }
+        }
+    }
+}
+
 }  // namespace gemm_detail
 }  // namespace psr

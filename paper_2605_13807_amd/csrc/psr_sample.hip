@@ -11,10 +11,10 @@
 //
 // One workgroup (8 waves) draws kS sequences.  Per site and layer the dense products are
 // FP32 MFMA GEMMs with the kS sequences as the N dimension (psr_gemm.h), over
-// the workgroup's workspace: the row frontier FR[l][i] (h^(l) of the row above
-// at column i), the horizontal state HH[l], and the activations X, Z, HT, PRE
-// ([d][kS] each, unit-major).  The sampled spins of the current and the
-// previous row stay in LDS.  Everything runs in FP32, whatever the model's
+// the workgroup's workspace -- the row frontier FR[l][i] (h^(l) of the row above
+// at column i) and the horizontal state HH[l] -- and over the activations X, Z,
+// HT, PRE of the site ([d][kS] each, unit-major), which stay in LDS with the
+// sampled spins of the current and the previous row.  Everything runs in FP32, whatever the model's
 // precision.  The chain (one layer, input the one-hot previous spin, head on h)
 // takes the same path with a one-site-high lattice, no vertical input and no
 // output block.
@@ -31,6 +31,7 @@ namespace {
 using namespace gemm_detail;
 
 constexpr int kS = 16;          // sequences per workgroup (the GEMM N dimension)
+constexpr int kMaxD = 256;      // largest model width
 constexpr int kThreads = 512;      // 8 waves: one 16-unit output tile each at d = 128
 constexpr int kLanesPerSeq = kThreads / kS;   // head: threads per sequence (a power of two <= 64)
 static_assert(kLanesPerSeq <= 64 && (kLanesPerSeq & (kLanesPerSeq - 1)) == 0, "head lanes per sequence");
@@ -60,10 +61,8 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
     const int DS = d * kS;
     float* FR = a.scratch + (int64_t)blockIdx.x * a.per_wg;   // [nl][lx][d][kS]
     float* HH = FR + (int64_t)nl * lx * DS;                    // [nl][d][kS]
-    float* X = HH + (int64_t)nl * DS;
-    float* Z = X + DS;
-    float* HT = Z + DS;
-    float* PRE = HT + DS;
+    // the activations of the site being drawn stay in LDS ([d][kS] each)
+    __shared__ float X[kMaxD * kS], Z[kMaxD * kS], HT[kMaxD * kS], PRE[kMaxD * kS];
     const float* th = a.theta;
 
     extern __shared__ int8_t sp[];   // [2][lx][kS]: spins of the previous and of the current row
@@ -133,9 +132,9 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
                         PRE[e] = (l >= 2) ? hb[e] : 0.0f;
                     }
                     __syncthreads();
-                    gemm(d, kS, d, MA{th + oWz, du, 1}, MB{X, kS, 1}, MC{Z, kS, 1}, true);
-                    gemm(d, kS, d, MA{th + oWh, ldh, 1}, MB{X, kS, 1}, MC{HT, kS, 1}, true);
-                    gemm(d, kS, d, MA{th + oD, du, 1}, MB{X, kS, 1}, MC{PRE, kS, 1}, true);
+                    gemm_lds_b(d, kS, d, MA{th + oWz, du, 1}, MB{X, kS, 1}, MC{Z, kS, 1}, true);
+                    gemm_lds_b(d, kS, d, MA{th + oWh, ldh, 1}, MB{X, kS, 1}, MC{HT, kS, 1}, true);
+                    gemm_lds_b(d, kS, d, MA{th + oD, du, 1}, MB{X, kS, 1}, MC{PRE, kS, 1}, true);
                 }
                 if (vp) {
                     if (l == 0) __syncthreads();
@@ -202,7 +201,7 @@ __global__ void __launch_bounds__(kThreads) sample_kernel(const SampleArgs a) {
 
 int64_t sample_ws_per_wg_floats(const Geom& g) {
     const int64_t DS = (int64_t)g.d * kS;
-    return (int64_t)g.nl * g.lx * DS + (int64_t)g.nl * DS + 4 * DS;
+    return (int64_t)g.nl * g.lx * DS + (int64_t)g.nl * DS;
 }
 
 int64_t sample_groups(int64_t B) { return (B + kS - 1) / kS; }
