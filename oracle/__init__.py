@@ -18,6 +18,8 @@ Modules
                  Hamiltonians from Pauli Kronecker products, exact spectra.
 ``sample``       exact autoregressive sampling with given uniforms, site by
                  site in the order of the factorisation.
+``lru``          the 1D LRU ansatz (complex diagonal recurrence, GLU, residual):
+                 parameter layout and log psi by the sequential recurrence.
 ``grad``         per-sample d log psi / d theta by float64 torch autograd on
                  the CPU (a second, separately written forward), central finite
                  differences of ``model``, and the VMC batch statistics.
@@ -26,4 +28,4 @@ Every function cites the passage of the paper it follows.  Pins (what fixes
 each function other than itself) live in ``tests/test_oracle_pins.py``.
 """
 
-from . import model, hamiltonian, sample  # noqa: F401
+from . import model, hamiltonian, sample, lru  # noqa: F401
