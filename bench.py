@@ -57,6 +57,12 @@ def flops_per_site(nl: int, d: int) -> float:
     return 2.0 * (2 * d * d + 5 * d * d * (nl - 1) + 2 * d)
 
 
+def lru_flops_per_site(nl: int, d: int, dh: int) -> float:
+    """Dense flops of one site of the 1D LRU: per layer the drive [B_re; B_im] x (2 dh x d),
+    the output map [C_re | C_im] (d x 2 dh) and the GLU's two projections (2 d x d), plus the head."""
+    return float(nl * (2 * (2 * dh * d) + 2 * (d * 2 * dh) + 2 * (2 * d * d)) + 2 * d)
+
+
 def fwd_source_sha() -> str:
     import hashlib
     with open(FWD_SOURCE, "rb") as f:
@@ -105,6 +111,7 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sampler", action="store_true", help="skip the sampler measurement")
+    ap.add_argument("--no-lru", action="store_true", help="skip the 1D LRU measurement")
     ap.add_argument("--chunk", type=int, default=32768)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM traffic counters)")
@@ -241,6 +248,42 @@ def main() -> int:
         print(f"# sampler: {ms_call:.1f} ms per {B} samples", file=sys.stderr, flush=True)
         del ws_s
 
+    # the 1D LRU ansatz of Table I (3 layers, d = d_h = 64) at N = 256: log psi of the
+    # E_loc batch of 1024 samples with their 256 single-flip TFIM configurations each,
+    # one kernel per call on the current stream, bracketed by events on that stream
+    lru = None
+    if not args.no_lru:
+        nL, nlL, dL, dhL, nsL = 256, 3, 64, 64, 1024
+        mL = P.LruModel(nL, nlL, dL, dhL)
+        thL = torch.from_numpy(I.params(P.lru_param_count(mL), dL, 3007)).to(dev)
+        sL = torch.from_numpy(I.spins_bernoulli(nsL, nL, 4007)).to(dev)
+        cL = P.connected(P.Hamiltonian(P.TFIM, nL, 1, J=1.0, h=1.0), sL, configs=True)
+        seqL = torch.cat([sL, cL["conn"].reshape(-1, nL)]).contiguous()
+        del cL
+        BL = seqL.shape[0]
+        wsL = torch.empty(P.lru_workspace_bytes(mL, BL), dtype=torch.uint8, device=dev)
+        P.lru_logpsi(mL, thL, seqL, ws=wsL)
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.lru_logpsi(mL, thL, seqL, ws=wsL)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_call = e0.elapsed_time(e1) / reps
+        fl = lru_flops_per_site(nlL, dL, dhL)
+        tfl = fl * nL * BL / (ms_call / 1000.0) / 1e12
+        lru = {"kernel": "lru_kernel",
+               "workload": f"tfim_chain{nL}: 1D LRU {nlL} layers d={dL} d_h={dhL}, {nsL} samples and their "
+                           f"{nL} single-flip configurations ({BL} chains)",
+               "chains": BL, "sites": nL, "ms_per_call": round(ms_call, 3),
+               "site_evals_per_s": BL * nL / (ms_call / 1000.0), "dtype": "f32",
+               "flops_per_site_eval": fl, "bound": "mfma", "achieved": round(tfl, 2),
+               "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s", "frac": round(tfl / PEAK["fp32_tflops"], 4)}
+        print(f"# lru: {ms_call:.2f} ms per {BL} chains of {nL}", file=sys.stderr, flush=True)
+        del wsL, seqL
+
     # CPU oracle baseline on a bounded sample, and the E_loc error on that sample
     cpu = None
     err = None
@@ -309,6 +352,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "fp32_path": fp32,
         "sampler": sampler,
+        "lru": lru,
         "error": err,
     }
     print(json.dumps(line))

@@ -204,6 +204,53 @@ int psr_sample(const psr_model_desc* m, const float* theta, const float* uniform
 /* Synchronous check of a spin batch: PSR_OK if every value is 0 or 1, PSR_EDATA otherwise. */
 int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream);
 
+/* ---- 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.E) -- */
+
+typedef struct {
+    int32_t n;          /* chain length N, 1 .. 16384 */
+    int32_t n_layers;   /* 1 .. 8 */
+    int32_t d;          /* width of each layer's input and output: a multiple of 16 in 16 .. 256 */
+    int32_t d_h;        /* complex hidden units per layer: a multiple of 16 in 16 .. 256 */
+} psr_lru_desc;
+
+/*
+ * Parameter layout (one flat float vector; matrices row-major, output index first):
+ *   E[d][2]                 embedding of the previous spin: the layer-0 input at
+ *                           site t is E[:, sigma_{t-1}], zero at t = 0
+ *   for each layer l:
+ *     nu[d_h], theta[d_h], gamma[d_h]   lambda = exp(-e^nu + i e^theta); drive scale e^gamma
+ *     B[2 d_h][d]           rows 0..d_h-1 the real part, then the imaginary part
+ *     D[d]
+ *     C[d][2 d_h]           columns 0..d_h-1 the real part, then the imaginary part
+ *     W_glu[2 d][d], b_glu[2 d]   rows 0..d-1 the GLU value projection, then its gate
+ *   W_o[2][d], b_o[2]       two-way softmax head on the last layer's output
+ * With 3 layers and d = d_h = 64 this is 75,138 parameters (Table I: about 75,000).
+ */
+int64_t psr_lru_param_count(const psr_lru_desc* m);   /* P, or a negative code */
+
+/* Device workspace bytes that psr_lru_logpsi needs for `batch` chains; negative on error. */
+int64_t psr_lru_workspace_bytes(const psr_lru_desc* m, int64_t batch);
+
+/*
+ * log psi of a batch of chains under the 1D LRU ansatz.  Per layer
+ *   h_t = lambda h_{t-1} + e^gamma (B x_t),  h_{-1} = 0,   y_t = Re(C h_t) + D x_t,
+ *   x'_t = (W_a y_t + b_a) sigmoid(W_g y_t + b_g) + [l >= 1] x_t,
+ * then log psi = 1/2 sum_t log p(sigma_t | sigma_<t) from the head (Sec. III.B).
+ * The recurrence runs as a chunked parallel scan over the chain (Sec. II.B); all
+ * arithmetic is FP32 (FP32 MFMA for the projections), the final sum FP64.
+ *   theta      device, float[P]
+ *   spins      device, int8[B][N] with values in {0, 1} (only the low bit is read;
+ *              psr_check_spins validates a batch)
+ *   logpsi     device, float[B]               (out)
+ *   logp_site  device, float[B][N] or NULL    (out) log p of each site
+ *   ws         device workspace of psr_lru_workspace_bytes(m, B) bytes, owned by the caller
+ * Errors: PSR_EINVAL (descriptor or pointer), PSR_ENOMEM (workspace too small),
+ * PSR_EDEVICE (launch).  The work is queued on `stream`; the call does not wait for it.
+ * Forward timing (psr_timing_begin) covers this kernel's launches too.
+ */
+int psr_lru_logpsi(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B,
+                   float* logpsi, float* logp_site, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Timing of the forward (log psi) kernel, for measurement tools.  After

@@ -83,6 +83,26 @@ class Hamiltonian:
         return _HamDesc(self.kind, self.lx, self.ly, int(self.marshall), int(self.pbc), float(self.J), float(self.h))
 
 
+class _LruDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("d", ctypes.c_int32), ("d_h", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class LruModel:
+    """The 1D LRU ansatz: chain length n, layers, width d and complex hidden units d_h."""
+    n: int
+    n_layers: int
+    d: int
+    d_h: int
+
+    def c(self) -> _LruDesc:
+        return _LruDesc(self.n, self.n_layers, self.d, self.d_h)
+
+    @property
+    def n_sites(self) -> int:
+        return self.n
+
+
 _lib = None
 
 
@@ -117,6 +137,12 @@ def lib() -> ctypes.CDLL:
         L.psr_gradient_estimate.restype = ctypes.c_int
         L.psr_vmc_weights.argtypes = [vp, vp, i64, vp, vp]
         L.psr_vmc_weights.restype = ctypes.c_int
+        L.psr_lru_param_count.argtypes = [P(_LruDesc)]
+        L.psr_lru_param_count.restype = i64
+        L.psr_lru_workspace_bytes.argtypes = [P(_LruDesc), i64]
+        L.psr_lru_workspace_bytes.restype = i64
+        L.psr_lru_logpsi.argtypes = [P(_LruDesc), vp, vp, i64, vp, vp, vp, sz, vp]
+        L.psr_lru_logpsi.restype = ctypes.c_int
         L.psr_check_spins.argtypes = [vp, i64, vp]
         L.psr_check_spins.restype = ctypes.c_int
         L.psr_timing_begin.argtypes = []
@@ -190,6 +216,37 @@ def logpsi(m: Model, theta: torch.Tensor, spins: torch.Tensor, site_logp: bool =
         ws = _workspace(m, OP_LOGPSI, B, spins.device)
     _check(lib().psr_logpsi(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps), _ptr(ws),
                             ws.numel(), _stream(spins.device)))
+    return (out, lps) if site_logp else out
+
+
+def lru_param_count(m: LruModel) -> int:
+    n = lib().psr_lru_param_count(ctypes.byref(m.c()))
+    _check(int(n) if n < 0 else 0)
+    return int(n)
+
+
+def lru_workspace_bytes(m: LruModel, batch: int) -> int:
+    n = lib().psr_lru_workspace_bytes(ctypes.byref(m.c()), batch)
+    _check(int(n) if n < 0 else 0)
+    return int(n)
+
+
+def lru_logpsi(m: LruModel, theta: torch.Tensor, spins: torch.Tensor, site_logp: bool = False,
+               ws: torch.Tensor | None = None):
+    """log psi [B] (float32) of chains under the 1D LRU ansatz, and the per-site log p [B, N] if ``site_logp``."""
+    theta = _dev(theta, torch.float32, "theta")
+    spins = _dev(spins, torch.int8, "spins")
+    B = spins.shape[0]
+    if spins.dim() != 2 or spins.shape[1] != m.n:
+        raise ValueError(f"spins must be [B, {m.n}], got {list(spins.shape)}")
+    if theta.numel() != lru_param_count(m):
+        raise ValueError(f"theta has {theta.numel()} entries, the model {lru_param_count(m)}")
+    out = torch.empty(B, dtype=torch.float32, device=spins.device)
+    lps = torch.empty(B, m.n, dtype=torch.float32, device=spins.device) if site_logp else None
+    if ws is None:
+        ws = torch.empty(max(1, lru_workspace_bytes(m, B)), dtype=torch.uint8, device=spins.device)
+    _check(lib().psr_lru_logpsi(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps), _ptr(ws),
+                                ws.numel(), _stream(spins.device)))
     return (out, lps) if site_logp else out
 
 

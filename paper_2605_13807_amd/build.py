@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpsr.so")
-SOURCES = ["psr_api.hip", "psr_fwd.hip", "psr_ham.hip", "psr_bwd.hip", "psr_sample.hip"]
+SOURCES = ["psr_api.hip", "psr_fwd.hip", "psr_ham.hip", "psr_bwd.hip", "psr_sample.hip", "psr_lru.hip"]
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in device code (the host pass of
 # hipcc warns that it does not know the feature; that is harmless).

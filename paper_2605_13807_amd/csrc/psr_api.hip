@@ -594,6 +594,57 @@ int psr_vmc_weights(const double* eloc, const double* stats, int64_t B, double* 
     return ok();
 }
 
+static int check_lru(const psr_lru_desc* m, LruGeom* g) {
+    if (!m) return fail(PSR_EINVAL, "LRU descriptor is NULL");
+    if (m->n < 1 || m->n > 16384) return fail(PSR_EINVAL, "chain length %d outside [1, 16384]", m->n);
+    if (m->n_layers < 1 || m->n_layers > 8) return fail(PSR_EINVAL, "n_layers %d outside [1, 8]", m->n_layers);
+    if (m->d < 16 || m->d > 256 || m->d % 16) return fail(PSR_EINVAL, "d = %d is not a multiple of 16 in [16, 256]", m->d);
+    if (m->d_h < 16 || m->d_h > 256 || m->d_h % 16)
+        return fail(PSR_EINVAL, "d_h = %d is not a multiple of 16 in [16, 256]", m->d_h);
+    g->n = m->n;
+    g->nl = m->n_layers;
+    g->d = m->d;
+    g->dh = m->d_h;
+    return PSR_OK;
+}
+
+int64_t psr_lru_param_count(const psr_lru_desc* m) {
+    LruGeom g;
+    const int r = check_lru(m, &g);
+    if (r) return r;
+    ok();
+    return lru_param_count(g);
+}
+
+int64_t psr_lru_workspace_bytes(const psr_lru_desc* m, int64_t batch) {
+    LruGeom g;
+    const int r = check_lru(m, &g);
+    if (r) return r;
+    if (batch < 0) return fail(PSR_EINVAL, "negative batch");
+    ok();
+    return lru_workspace_floats(g, batch) * (int64_t)sizeof(float);
+}
+
+int psr_lru_logpsi(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
+                   float* logp_site, void* ws, size_t ws_bytes, void* stream) {
+    LruGeom g;
+    int r = check_lru(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !spins || !logpsi) return fail(PSR_EINVAL, "theta, spins and logpsi must not be NULL");
+    const int64_t need = lru_workspace_floats(g, B) * (int64_t)sizeof(float);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    hipStream_t st = as_stream(stream);
+    hipEvent_t stop;
+    timing_before(st, &stop);
+    const int e = launch_lru_logpsi(g, theta, spins, B, logpsi, logp_site, static_cast<float*>(ws), st);
+    if (stop && hipEventRecord(stop, st) != hipSuccess) --g_tm.used;   // drop the half-recorded pair
+    if ((r = dev_check(e, "LRU forward"))) return r;
+    return ok();
+}
+
 int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream) {
     if (n_values < 0) return fail(PSR_EINVAL, "negative size");
     if (n_values == 0) return ok();

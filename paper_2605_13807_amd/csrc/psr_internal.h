@@ -138,4 +138,18 @@ int launch_backward(const Geom& g, const BwdLayout& bl, const float* theta, cons
                     int64_t B, float* wt, float* scratch, float* O, float* logpsi, hipStream_t st);
 int launch_weighted_sum(const float* O, int64_t B, int64_t P, const double* w, double* g, hipStream_t st);
 
+// 1D LRU ansatz (psr_lru.hip)
+struct LruGeom {
+    int n, nl, d, dh;   // chain length, layers, width, hidden (complex) units
+};
+// floats of one layer: nu, theta, gamma [dh]; B [2 dh][d]; D [d]; C [d][2 dh]; W_glu [2 d][d]; b_glu [2 d]
+__host__ __device__ inline int64_t lru_layer_floats(const LruGeom& g) {
+    const int64_t d = g.d, dh = g.dh;
+    return 3 * dh + 2 * dh * d + d + 2 * d * dh + 2 * d * d + 2 * d;
+}
+int64_t lru_param_count(const LruGeom& g);
+int64_t lru_workspace_floats(const LruGeom& g, int64_t B);
+int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
+                      float* logp_site, float* scratch, hipStream_t st);
+
 }  // namespace psr

@@ -1,0 +1,265 @@
+// log psi of the 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.E).
+//
+// Per layer, with the layer input x_t in R^d at every site t of the chain:
+//   lambda = exp(-e^nu + i e^theta),  h_t = lambda h_{t-1} + e^gamma (B x_t),  h_{-1} = 0,
+//   y_t = Re(C h_t) + D x_t,  x'_t = (W_a y_t + b_a) sigmoid(W_g y_t + b_g) + [l >= 1] x_t.
+// The layer-0 input at site t is the embedding E[:, sigma_{t-1}] (zero at t = 0),
+// and the head is a two-way softmax on the last layer's output; log psi is half
+// the sum of the sites' log p (Sec. III.B).
+//
+// One workgroup (8 waves) takes S sequences at a time, S N columns (S = 256 / N
+// for short chains, else 1).  The activations of the group live in the
+// workgroup's workspace, unit-major ([units][columns]):
+//   * drive:   U = [B_re; B_im] X                 one FP32 MFMA GEMM, M = 2 d_h
+//   * scan:    the recurrence is linear with a constant diagonal coefficient, so
+//              each (sequence, unit) is cut into chunks that are scanned from a
+//              zero state in parallel; the chunks' end states are chained with
+//              lambda^len, and every element then gets lambda^(t - t0 + 1) times
+//              its chunk's carry (Sec. II.B: the LRU hidden states by a parallel scan)
+//   * output:  Y = D x + [C_re | C_im] [h_re; -h_im]   one GEMM, K = 2 d_h
+//   * GLU:     G = W_glu Y + b_glu                     one GEMM, M = 2 d
+//   * gate, residual, then the head and a per-sequence FP64 sum.
+// Every step runs in FP32; the GEMMs are the dense part of the layer.
+
+#include <hip/hip_runtime.h>
+
+#include "psr_gemm.h"
+#include "psr_internal.h"
+
+namespace psr {
+
+namespace {
+
+using namespace gemm_detail;
+
+constexpr int kThreads = 512;
+constexpr int kColTarget = 256;     // columns per group for short chains
+constexpr int64_t kMaxGroupsInFlight = 1024;
+
+struct LruArgs {
+    LruGeom g;
+    const float* theta;
+    const int8_t* spins;   // [B][N]
+    int64_t B;
+    int S;                 // sequences per group
+    int64_t groups;
+    float* logpsi;         // [B]
+    float* logp_site;      // [B][N] or null
+    float* scratch;
+    int64_t per_wg;        // floats of workspace per workgroup
+};
+
+__device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
+__device__ inline float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+__global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
+    const LruGeom& G = a.g;
+    const int N = G.n, d = G.d, dh = G.dh, nl = G.nl, S = a.S;
+    const int cols = S * N;
+    const int tid = threadIdx.x;
+    float* X = a.scratch + (int64_t)blockIdx.x * a.per_wg;   // [d][cols]
+    float* U = X + (int64_t)d * cols;                          // [2 dh][cols]
+    float* Y = U + (int64_t)2 * dh * cols;                     // [d][cols]
+    float* GL = Y + (int64_t)d * cols;                         // [2 d][cols]
+    const float* th = a.theta;
+    const int64_t lstride = lru_layer_floats(G);
+    const float* Wo = th + (int64_t)2 * d + nl * lstride;
+    const float* bo = Wo + 2 * d;
+
+    __shared__ float2 endst[kThreads], carry[kThreads];
+    __shared__ double red[kThreads];
+
+    // chunks per (sequence, unit) of the scan; items * nch <= kThreads when nch > 1
+    const int items = dh * S;
+    const int nch = items >= kThreads ? 1 : min(N, kThreads / items);
+    const int Lc = (N + nch - 1) / nch;
+
+    for (int64_t grp = blockIdx.x; grp < a.groups; grp += gridDim.x) {
+        const int64_t q0 = grp * S;
+        // layer-0 input: E[:, sigma_{t-1}], zero at t = 0 and for sequences past B
+        for (int e = tid; e < d * cols; e += kThreads) {
+            const int m = e / cols, col = e - m * cols;
+            const int s = col / N, t = col - s * N;
+            const int64_t q = q0 + s;
+            float x = 0.0f;
+            if (t > 0 && q < a.B) x = th[m * 2 + (a.spins[q * N + t - 1] & 1)];
+            X[e] = x;
+        }
+        __syncthreads();
+        for (int l = 0; l < nl; ++l) {
+            const float* Lp = th + (int64_t)2 * d + l * lstride;
+            const float* nu = Lp;
+            const float* ph = Lp + dh;
+            const float* gm = Lp + 2 * dh;
+            const float* Bm = Lp + 3 * dh;                 // [2 dh][d]
+            const float* Dv = Bm + (int64_t)2 * dh * d;    // [d]
+            const float* Cm = Dv + d;                      // [d][2 dh]
+            const float* Wg = Cm + (int64_t)2 * dh * d;    // [2 d][d]
+            const float* bg = Wg + (int64_t)2 * d * d;     // [2 d]
+            // drive B x (the e^gamma scale is applied in the scan)
+            gemm(2 * dh, cols, d, MA{Bm, d, 1}, MB{X, cols, 1}, MC{U, cols, 1}, false);
+            __syncthreads();
+            // scan, phase 1: every chunk from a zero state
+            for (int w = tid; w < items * nch; w += kThreads) {
+                const int it = w % items, c = w / items;
+                const int u = it % dh, s = it / dh;
+                const int t0 = c * Lc, t1 = min(N, t0 + Lc);
+                const float mag = expf(-expf(nu[u]));
+                float sn, cs;
+                sincosf(expf(ph[u]), &sn, &cs);
+                const float lr = mag * cs, li = mag * sn, gg = expf(gm[u]);
+                float* ur = U + (int64_t)u * cols + s * N;
+                float* ui = U + (int64_t)(dh + u) * cols + s * N;
+                float hr = 0.0f, hi = 0.0f;
+                for (int t = t0; t < t1; ++t) {
+                    const float nr = fmaf(lr, hr, fmaf(-li, hi, gg * ur[t]));
+                    const float ni = fmaf(lr, hi, fmaf(li, hr, gg * ui[t]));
+                    hr = nr;
+                    hi = ni;
+                    ur[t] = hr;
+                    ui[t] = (nch == 1) ? -hi : hi;   // one chunk: final, -Im for the output GEMM
+                }
+                if (nch > 1) endst[w] = make_float2(hr, hi);
+            }
+            if (nch > 1) {
+                __syncthreads();
+                // phase 2: carry into chunk c = state after chunk c - 1 (lambda^len chains the ends)
+                for (int it = tid; it < items; it += kThreads) {
+                    const int u = it % dh;
+                    const float a_ = expf(nu[u]), b_ = expf(ph[u]);
+                    float cr = 0.0f, ci = 0.0f;
+                    for (int c = 0; c < nch; ++c) {
+                        carry[c * items + it] = make_float2(cr, ci);
+                        const int t0 = c * Lc, len = max(0, min(N, t0 + Lc) - t0);
+                        const float mag = expf(-(float)len * a_);
+                        float sn, cs;
+                        sincosf((float)len * b_, &sn, &cs);
+                        const float pr = mag * cs, pi = mag * sn;
+                        const float2 e = endst[c * items + it];
+                        const float nr = pr * cr - pi * ci + e.x;
+                        const float ni = pr * ci + pi * cr + e.y;
+                        cr = nr;
+                        ci = ni;
+                    }
+                }
+                __syncthreads();
+                // phase 3: h_t += lambda^(t - t0 + 1) carry
+                for (int w = tid; w < items * nch; w += kThreads) {
+                    const int it = w % items, c = w / items;
+                    const int u = it % dh, s = it / dh;
+                    const int t0 = c * Lc, t1 = min(N, t0 + Lc);
+                    const float mag = expf(-expf(nu[u]));
+                    float sn, cs;
+                    sincosf(expf(ph[u]), &sn, &cs);
+                    const float lr = mag * cs, li = mag * sn;
+                    const float2 cin = carry[w];
+                    float* ur = U + (int64_t)u * cols + s * N;
+                    float* ui = U + (int64_t)(dh + u) * cols + s * N;
+                    float pr = lr, pi = li;
+                    for (int t = t0; t < t1; ++t) {
+                        ur[t] += pr * cin.x - pi * cin.y;
+                        ui[t] = -(ui[t] + pr * cin.y + pi * cin.x);
+                        const float np = pr * lr - pi * li;
+                        pi = pr * li + pi * lr;
+                        pr = np;
+                    }
+                }
+            }
+            // seeds: y = D x, and the GLU biases
+            for (int e = tid; e < d * cols; e += kThreads) Y[e] = Dv[e / cols] * X[e];
+            for (int e = tid; e < 2 * d * cols; e += kThreads) GL[e] = bg[e / cols];
+            __syncthreads();
+            // y += Re(C h) = C_re h_re + C_im (-h_im)
+            gemm(d, cols, 2 * dh, MA{Cm, 2 * dh, 1}, MB{U, cols, 1}, MC{Y, cols, 1}, true);
+            __syncthreads();
+            gemm(2 * d, cols, d, MA{Wg, d, 1}, MB{Y, cols, 1}, MC{GL, cols, 1}, true);
+            __syncthreads();
+            // GLU and the residual (from the second layer on)
+            for (int e = tid; e < d * cols; e += kThreads) {
+                const float v = GL[e] * sigm(GL[e + (int64_t)d * cols]);
+                X[e] = (l >= 1) ? X[e] + v : v;
+            }
+            __syncthreads();
+        }
+        // head: logit(0) - logit(1) per column; log p of the own spin into GL's first row
+        for (int col = tid; col < cols; col += kThreads) {
+            const int s = col / N, t = col - s * N;
+            const int64_t q = q0 + s;
+            float dl = bo[0] - bo[1];
+            for (int m = 0; m < d; ++m) dl = fmaf(Wo[m] - Wo[d + m], X[(int64_t)m * cols + col], dl);
+            float lp = 0.0f;
+            if (q < a.B) {
+                const int own = a.spins[q * N + t] & 1;
+                lp = -softplus(own ? dl : -dl);
+                if (a.logp_site) a.logp_site[q * N + t] = lp;
+            }
+            GL[col] = lp;
+        }
+        __syncthreads();
+        if (S == 1) {
+            double acc = 0.0;
+            for (int t = tid; t < N; t += kThreads) acc += (double)GL[t];
+            red[tid] = acc;
+            __syncthreads();
+            for (int w = kThreads / 2; w >= 1; w >>= 1) {
+                if (tid < w) red[tid] += red[tid + w];
+                __syncthreads();
+            }
+            if (tid == 0 && q0 < a.B) a.logpsi[q0] = (float)(0.5 * red[0]);
+        } else if (tid < S && q0 + tid < a.B) {
+            double acc = 0.0;
+            for (int t = 0; t < N; ++t) acc += (double)GL[tid * N + t];
+            a.logpsi[q0 + tid] = (float)(0.5 * acc);
+        }
+        __syncthreads();   // the next group overwrites the workspace
+    }
+}
+
+int lru_seqs_per_group(const LruGeom& g) { return g.n >= kColTarget ? 1 : kColTarget / g.n; }
+
+int64_t lru_per_wg_floats(const LruGeom& g) {
+    const int64_t cols = (int64_t)lru_seqs_per_group(g) * g.n;
+    return ((int64_t)4 * g.d + (int64_t)2 * g.dh) * cols;
+}
+
+int64_t lru_grid(const LruGeom& g, int64_t B) {
+    const int S = lru_seqs_per_group(g);
+    const int64_t groups = (B + S - 1) / S;
+    // at most kMaxGroupsInFlight workgroups, fewer when a group's workspace is large
+    // (but never fewer than one per compute unit)
+    const int64_t by_mem = ((int64_t)1 << 30) / (lru_per_wg_floats(g) * (int64_t)sizeof(float));
+    int64_t cap = by_mem < kMaxGroupsInFlight ? by_mem : kMaxGroupsInFlight;
+    if (cap < 256) cap = 256;
+    return groups < cap ? groups : cap;
+}
+
+}  // namespace
+
+int64_t lru_param_count(const LruGeom& g) {
+    return (int64_t)2 * g.d + g.nl * lru_layer_floats(g) + (int64_t)2 * g.d + 2;
+}
+
+int64_t lru_workspace_floats(const LruGeom& g, int64_t B) {
+    if (B <= 0) return 0;
+    return lru_grid(g, B) * lru_per_wg_floats(g);
+}
+
+int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
+                      float* logp_site, float* scratch, hipStream_t st) {
+    if (B == 0) return 0;
+    LruArgs a;
+    a.g = g;
+    a.theta = theta;
+    a.spins = spins;
+    a.B = B;
+    a.S = lru_seqs_per_group(g);
+    a.groups = (B + a.S - 1) / a.S;
+    a.logpsi = logpsi;
+    a.logp_site = logp_site;
+    a.scratch = scratch;
+    a.per_wg = lru_per_wg_floats(g);
+    hipLaunchKernelGGL(lru_kernel, dim3((unsigned)lru_grid(g, B)), dim3(kThreads), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace psr

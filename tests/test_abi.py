@@ -129,3 +129,28 @@ def test_workspace_sizes_grow_with_batch(P):
         b = P.workspace_bytes(m, op, 200, 1000)
         assert 0 < a < b
 
+
+
+def test_lru_layout_and_host_checks(P):
+    from oracle import lru as OL
+    for n, nl, d, dh in ((256, 3, 64, 64), (8, 1, 16, 32), (100, 2, 32, 16), (1, 8, 256, 256)):
+        assert P.lru_param_count(P.LruModel(n, nl, d, dh)) == OL.n_params(OL.LruModel(n, nl, d, dh))
+    assert P.lru_param_count(P.LruModel(64, 3, 64, 64)) == 75138
+    L = P.lib()
+    for bad in ((0, 1, 64, 64), (16385, 1, 64, 64), (8, 0, 64, 64), (8, 9, 64, 64), (8, 1, 24, 64),
+                (8, 1, 64, 8), (8, 1, 272, 64)):
+        assert L.psr_lru_param_count(ctypes.byref(P.LruModel(*bad).c())) == -1, bad
+    assert L.psr_lru_param_count(None) == -1
+    m = P.LruModel(256, 3, 64, 64).c()
+    fake = ctypes.c_void_p(16)
+    assert L.psr_lru_workspace_bytes(ctypes.byref(m), -1) == -1
+    assert L.psr_lru_workspace_bytes(ctypes.byref(m), 0) == 0
+    small, big = (L.psr_lru_workspace_bytes(ctypes.byref(m), b) for b in (3, 300000))
+    assert 0 < small <= big
+    # NULL outputs, workspace too small, negative batch: rejected before any launch
+    assert L.psr_lru_logpsi(ctypes.byref(m), fake, fake, 4, None, None, fake, 1 << 40, None) == -1
+    assert L.psr_lru_logpsi(ctypes.byref(m), fake, fake, 4, fake, None, fake, 16, None) == -3
+    assert L.psr_lru_logpsi(ctypes.byref(m), fake, fake, 4, fake, None, None, 1 << 40, None) == -3
+    assert L.psr_lru_logpsi(ctypes.byref(m), fake, fake, -1, fake, None, fake, 1 << 40, None) == -1
+    assert L.psr_lru_logpsi(ctypes.byref(m), None, None, 0, None, None, None, 0, None) == 0
+    assert L.psr_last_error() == b""

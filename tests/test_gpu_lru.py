@@ -1,0 +1,120 @@
+"""GPU parity of the 1D LRU ansatz (Sec. II.B Eq. (lru), Sec. II.E) through the C ABI.
+
+The library's FP32 log psi and per-site log p against the float64 oracle
+(``oracle/lru.py``), element by element, with the tolerances of the 2D forward
+tests: |d log psi| <= 1e-5 + 1e-6 max|log psi| and 1e-4 per site.  The cases
+cover every path of the kernel: short chains packed many to a group with
+unchunked scans, chunked scans with a ragged last chunk, one chain per group,
+one-site chains, more groups than workgroups in flight, the paper's Table I
+model (3 layers, d = d_h = 64) at N = 6 and N = 256, and the full E_loc batch
+of that model at N = 256 on sampled outputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import psr_inputs as I
+from oracle import lru as OL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_13807_amd as P  # noqa: N813
+    P.lib()
+    return P
+
+
+def _case(P, n, nl, d, dh, B, seed):
+    m = P.LruModel(n, nl, d, dh)
+    om = OL.LruModel(n, nl, d, dh)
+    assert P.lru_param_count(m) == OL.n_params(om)
+    th = I.params(OL.n_params(om), d, 3000 + seed)
+    s = I.spins_bernoulli(B, n, 4000 + seed)
+    return m, om, th, s
+
+
+def _tol(ref):
+    return 1e-5 + 1e-6 * float(np.abs(ref).max())
+
+
+LRU_CASES = [
+    # n, nl, d, dh, B
+    (16, 1, 16, 32, 33),       # 16 chains per group, one scan chunk per chain
+    (6, 3, 64, 64, 100),       # the Table I model at N = 6; ragged last group
+    (100, 2, 32, 16, 7),       # 2 chains per group, 16 chunks of 7 sites (ragged last chunk)
+    (256, 3, 64, 64, 5),       # the Table I model at N = 256: one chain per group, 8 chunks
+    (257, 2, 32, 32, 3),       # one site past a group's columns
+    (1, 2, 16, 16, 9),         # one-site chains: only the head's bias and the zero input
+    (1000, 1, 64, 256, 2),     # long chains, 256 complex units: 2 chunks of 500
+    (16, 1, 16, 32, 20000),    # 1250 groups over at most 1024 workgroups
+]
+
+
+@pytest.mark.parametrize("n,nl,d,dh,B", LRU_CASES)
+def test_lru_logpsi_parity(P, n, nl, d, dh, B):
+    print(f"LRU case n={n} nl={nl} d={d} dh={dh} B={B}", flush=True)
+    m, om, th, s = _case(P, n, nl, d, dh, B, seed=n + nl + d)
+    ref_site = OL.site_logp(th, s, om)
+    ref = 0.5 * ref_site.sum(axis=1)
+    got, site = P.lru_logpsi(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda(), site_logp=True)
+    got = got.cpu().numpy().astype(np.float64)
+    site = site.cpu().numpy().astype(np.float64)
+    err, serr = np.abs(got - ref).max(), np.abs(site - ref_site).max()
+    print(f"  max|dlogpsi| = {err:.3e} (tol {_tol(ref):.3e}); max site err {serr:.3e}; |log psi| ~ {np.abs(ref).max():.1f}")
+    assert err <= _tol(ref)
+    assert serr <= 1e-4
+
+
+def test_lru_batch_position_invariance_and_empty(P):
+    m, om, th, s = _case(P, 40, 2, 32, 32, 61, seed=1)
+    tt, ss = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
+    a = P.lru_logpsi(m, tt, ss)
+    perm = torch.randperm(61, generator=torch.Generator().manual_seed(0)).cuda()
+    c = P.lru_logpsi(m, tt, ss[perm])
+    # each chain's arithmetic does not depend on its position in the batch
+    assert torch.equal(c, a[perm])
+    assert P.lru_logpsi(m, tt, ss[:0]).numel() == 0
+
+
+def test_lru_normalised_over_all_configurations(P):
+    """sum over all 2^N configurations of psi^2 = 1, from the library alone (N = 12)."""
+    n = 12
+    m, om, th, _ = _case(P, n, 3, 32, 32, 1, seed=2)
+    idx = np.arange(2 ** n)
+    allc = ((idx[:, None] >> np.arange(n)[None, :]) & 1).astype(np.int8)
+    lp = P.lru_logpsi(m, torch.from_numpy(th).cuda(), torch.from_numpy(allc).cuda()).double()
+    total = torch.exp(2.0 * lp).sum().item()
+    print(f"  sum psi^2 = {total:.9f}")
+    assert abs(total - 1.0) <= 1e-4
+
+
+def test_lru_full_eloc_batch_sampled(P):
+    """The Table I model at N = 256 on the E_loc batch of 1024 samples (each with its 256
+    single-flip TFIM configurations: 263,168 chains), in the launch that the benchmark
+    times; sampled chains against the oracle, the rest through the flip structure."""
+    n, nl, d, dh, nsamp = 256, 3, 64, 64, 1024
+    m = P.LruModel(n, nl, d, dh)
+    om = OL.LruModel(n, nl, d, dh)
+    th = I.params(OL.n_params(om), d, 3000 + 7)
+    s = torch.from_numpy(I.spins_bernoulli(nsamp, n, 4000 + 7)).cuda()
+    H = P.Hamiltonian(P.TFIM, n, 1, J=1.0, h=1.0)
+    c = P.connected(H, s, configs=True)
+    assert int(c["n_conn"].min().item()) == n
+    seqs = torch.cat([s, c["conn"].reshape(-1, n)], dim=0).contiguous()
+    print(f"LRU full batch: {seqs.shape[0]} chains of {n} sites", flush=True)
+    lp = P.lru_logpsi(m, torch.from_numpy(th).cuda(), seqs)
+    assert bool(torch.isfinite(lp).all())
+    picks = [0, nsamp - 1, nsamp, nsamp + 255, seqs.shape[0] - 1, 123457]
+    sub = seqs[picks].cpu().numpy()
+    ref = OL.logpsi(th, sub, om)
+    got = lp[picks].double().cpu().numpy()
+    err = np.abs(got - ref).max()
+    print(f"  sampled chains: max|dlogpsi| = {err:.3e}")
+    assert err <= _tol(ref)
+    # the same chains evaluated alone, in a small launch: identical values
+    alone = P.lru_logpsi(m, torch.from_numpy(th).cuda(), seqs[picks].contiguous())
+    assert torch.equal(alone, lp[picks])
