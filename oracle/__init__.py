@@ -25,7 +25,8 @@ Modules
                  differences of ``model``, and the VMC batch statistics.
 
 Every function cites the passage of the paper it follows.  Pins (what fixes
-each function other than itself) live in ``tests/test_oracle_pins.py``.
+each function other than itself) live in ``tests/test_oracle_pins.py`` and
+``tests/test_oracle_lru_pins.py``.
 """
 
 from . import model, hamiltonian, sample, lru  # noqa: F401
