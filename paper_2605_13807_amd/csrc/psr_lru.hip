@@ -16,7 +16,7 @@
 //              zero state in parallel; the chunks' end states are chained with
 //              lambda^len, and every element then gets lambda^(t - t0 + 1) times
 //              its chunk's carry (Sec. II.B: the LRU hidden states by a parallel scan)
-//   * output:  Y = D x + [C_re | C_im] [h_re; -h_im]   one GEMM, K = 2 d_h
+//   * output:  Y = D x + C_re h_re + C_im (-h_im)      two GEMM passes, K = d_h each
 //   * GLU:     G = W_glu Y + b_glu                     one GEMM, M = 2 d
 //   * gate, residual, then the head and a per-sequence FP64 sum.
 // Every step runs in FP32; the GEMMs are the dense part of the layer.
@@ -34,6 +34,8 @@ using namespace gemm_detail;
 
 constexpr int kThreads = 512;
 constexpr int kColTarget = 256;     // columns per group for short chains
+constexpr int kR = 32;              // longest scan chunk held in registers
+constexpr int kB = 8;               // elementwise loops: loads in flight per thread
 constexpr int64_t kMaxGroupsInFlight = 1024;
 
 struct LruArgs {
@@ -51,6 +53,98 @@ struct LruArgs {
 
 __device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 __device__ inline float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+// C (+)= A B with A [M][K] (row stride lda; weights), B [K][ldb] and C [M][ldc] (workspace),
+// for K <= 4 kKQ.  A wave keeps the A fragment of its 16 output rows in registers
+// (K/4 floats a lane) across all of its column tiles, and issues the next tile's B
+// loads before the current tile's MFMAs.  Lane layout of the FP32 16x16x4 MFMA: a
+// lane holds A(m0 + lane%16, 4j + lane/16), B(4j + lane/16, n0 + lane%16) and
+// outputs rows m0 + 4 (lane/16) + i of column n0 + lane%16.  M is a multiple of 16;
+// N is masked (columns past N read column N - 1 and are not stored).  Called by
+// the whole workgroup; no barrier inside.
+constexpr int kKQ = 16;
+__device__ inline void gemm_ws(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
+                               int ldc, bool acc_in) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int kq = lane >> 4, r16 = lane & 15;
+    const int tm = M >> 4, tn = (N + 15) >> 4, KQ = K >> 2;
+    // waves -> tiles: with at least nw row tiles a wave takes every nw-th row tile and all
+    // column tiles; with fewer, nw / tm waves share a row tile and split its column tiles
+    int mt0 = wave, mstep = nw, nt0 = 0, nstep = 1;
+    if (tm < nw) {
+        const int wpm = nw / tm;
+        mt0 = wave / wpm;
+        mstep = nw;
+        nt0 = wave % wpm;
+        nstep = wpm;
+    }
+    for (int mt = mt0; mt < tm; mt += mstep) {
+        const int m0 = mt << 4;
+        float af[kKQ];
+        const float* ap = A + (int64_t)(m0 + r16) * lda + kq;
+#pragma unroll
+        for (int j = 0; j < kKQ; ++j) af[j] = (j < KQ) ? ap[4 * j] : 0.0f;
+        float bc[kKQ], bn[kKQ];
+        auto loadb = [&](int nt, float* b) {
+            const int n = min((nt << 4) + r16, N - 1);
+            const float* bp = B + (int64_t)kq * ldb + n;
+#pragma unroll
+            for (int j = 0; j < kKQ; ++j) b[j] = (j < KQ) ? bp[(int64_t)4 * j * ldb] : 0.0f;
+        };
+        if (nt0 < tn) loadb(nt0, bc);
+        for (int nt = nt0; nt < tn; nt += nstep) {
+            if (nt + nstep < tn) loadb(nt + nstep, bn);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < kKQ; ++j)
+                if (j < KQ) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j], bc[j], acc, 0, 0, 0);
+            const int n = (nt << 4) + r16;
+            if (n < N) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float* cp = C + (int64_t)(m0 + 4 * kq + i) * ldc + n;
+                    *cp = acc_in ? *cp + acc[i] : acc[i];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kKQ; ++j) bc[j] = bn[j];
+        }
+    }
+}
+
+// the weights-stationary GEMM where K fits its registers, the general one otherwise
+__device__ inline void gemm_lru(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
+                                int ldc, bool acc_in) {
+    if (K <= 4 * kKQ)
+        gemm_ws(M, N, K, A, lda, B, ldb, C, ldc, acc_in);
+    else
+        gemm(M, N, K, MA{A, lda, 1}, MB{B, ldb, 1}, MC{C, ldc, 1}, acc_in);
+}
+
+// scan phase 2: the carry into chunk c of item it (unit it % dh) is the state after
+// chunk c - 1; lambda^len in closed form, exp(-len e^nu) (cos, sin)(len e^theta), chains
+// the chunks' end states.  Called by the whole workgroup; no barrier inside.
+__device__ inline void lru_carries(const float* nu, const float* ph, int dh, int items, int nch, int Lc, int N,
+                                   const float2* endst, float2* carry) {
+    for (int it = threadIdx.x; it < items; it += kThreads) {
+        const int u = it % dh;
+        const float a_ = expf(nu[u]), b_ = expf(ph[u]);
+        float cr = 0.0f, ci = 0.0f;
+        for (int c = 0; c < nch; ++c) {
+            carry[c * items + it] = make_float2(cr, ci);
+            const int t0 = c * Lc, len = max(0, min(N, t0 + Lc) - t0);
+            const float mag = expf(-(float)len * a_);
+            float sn, cs;
+            sincosf((float)len * b_, &sn, &cs);
+            const float pr = mag * cs, pi = mag * sn;
+            const float2 e = endst[c * items + it];
+            const float nr = pr * cr - pi * ci + e.x;
+            const float ni = pr * ci + pi * cr + e.y;
+            cr = nr;
+            ci = ni;
+        }
+    }
+}
 
 __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
     const LruGeom& G = a.g;
@@ -77,13 +171,21 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
     for (int64_t grp = blockIdx.x; grp < a.groups; grp += gridDim.x) {
         const int64_t q0 = grp * S;
         // layer-0 input: E[:, sigma_{t-1}], zero at t = 0 and for sequences past B
-        for (int e = tid; e < d * cols; e += kThreads) {
-            const int m = e / cols, col = e - m * cols;
-            const int s = col / N, t = col - s * N;
-            const int64_t q = q0 + s;
-            float x = 0.0f;
-            if (t > 0 && q < a.B) x = th[m * 2 + (a.spins[q * N + t - 1] & 1)];
-            X[e] = x;
+        for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
+            float xv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                const int e = e0 + k * kThreads;
+                const int m = e / cols, col = e - m * cols;
+                const int s = col / N, t = col - s * N;
+                const int64_t q = q0 + s;
+                xv[k] = (e < d * cols && t > 0 && q < a.B) ? th[m * 2 + (a.spins[q * N + t - 1] & 1)] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                const int e = e0 + k * kThreads;
+                if (e < d * cols) X[e] = xv[k];
+            }
         }
         __syncthreads();
         for (int l = 0; l < nl; ++l) {
@@ -97,8 +199,78 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
             const float* Wg = Cm + (int64_t)2 * dh * d;    // [2 d][d]
             const float* bg = Wg + (int64_t)2 * d * d;     // [2 d]
             // drive B x (the e^gamma scale is applied in the scan)
-            gemm(2 * dh, cols, d, MA{Bm, d, 1}, MB{X, cols, 1}, MC{U, cols, 1}, false);
+            gemm_lru(2 * dh, cols, d, Bm, d, X, cols, U, cols, false);
             __syncthreads();
+            if (Lc <= kR) {
+                // chunks of at most kR sites: each is loaded in one burst, scanned in
+                // registers and, with several chunks, kept there across the carry step
+                // (then items * nch <= kThreads: one chunk per thread, one pass)
+                const int nwork = items * nch;
+                for (int w0 = 0; w0 < nwork; w0 += kThreads) {
+                    const int w = w0 + tid;
+                    const bool mine = w < nwork;
+                    float vr[kR], vi[kR];
+                    float lr = 0.0f, li = 0.0f;
+                    int len = 0;
+                    float* ur = U;
+                    float* ui = U;
+                    if (mine) {
+                        const int it = w % items, c = w / items;
+                        const int u = it % dh, s = it / dh;
+                        const int t0 = c * Lc;
+                        len = max(0, min(N, t0 + Lc) - t0);
+                        const float mag = expf(-expf(nu[u]));
+                        float sn, cs;
+                        sincosf(expf(ph[u]), &sn, &cs);
+                        lr = mag * cs;
+                        li = mag * sn;
+                        const float gg = expf(gm[u]);
+                        ur = U + (int64_t)u * cols + s * N + t0;
+                        ui = U + (int64_t)(dh + u) * cols + s * N + t0;
+#pragma unroll
+                        for (int j = 0; j < kR; ++j) {
+                            vr[j] = (j < len) ? ur[j] : 0.0f;
+                            vi[j] = (j < len) ? ui[j] : 0.0f;
+                        }
+                        float hr = 0.0f, hi = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < kR; ++j) {
+                            const float nr = fmaf(lr, hr, fmaf(-li, hi, gg * vr[j]));
+                            const float ni = fmaf(lr, hi, fmaf(li, hr, gg * vi[j]));
+                            hr = (j < len) ? nr : hr;
+                            hi = (j < len) ? ni : hi;
+                            vr[j] = hr;
+                            vi[j] = hi;
+                        }
+                        if (nch > 1) endst[w] = make_float2(hr, hi);
+                    }
+                    if (nch > 1) {
+                        __syncthreads();
+                        lru_carries(nu, ph, dh, items, nch, Lc, N, endst, carry);
+                        __syncthreads();
+                        if (mine) {
+                            const float2 cin = carry[w];
+                            float pr = lr, pi = li;
+#pragma unroll
+                            for (int j = 0; j < kR; ++j) {
+                                vr[j] += pr * cin.x - pi * cin.y;
+                                vi[j] += pr * cin.y + pi * cin.x;
+                                const float np = pr * lr - pi * li;
+                                pi = pr * li + pi * lr;
+                                pr = np;
+                            }
+                        }
+                    }
+                    if (mine) {
+#pragma unroll
+                        for (int j = 0; j < kR; ++j)
+                            if (j < len) {
+                                ur[j] = vr[j];
+                                ui[j] = -vi[j];
+                            }
+                    }
+                }
+            } else {
             // scan, phase 1: every chunk from a zero state
             for (int w = tid; w < items * nch; w += kThreads) {
                 const int it = w % items, c = w / items;
@@ -123,25 +295,7 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
             }
             if (nch > 1) {
                 __syncthreads();
-                // phase 2: carry into chunk c = state after chunk c - 1 (lambda^len chains the ends)
-                for (int it = tid; it < items; it += kThreads) {
-                    const int u = it % dh;
-                    const float a_ = expf(nu[u]), b_ = expf(ph[u]);
-                    float cr = 0.0f, ci = 0.0f;
-                    for (int c = 0; c < nch; ++c) {
-                        carry[c * items + it] = make_float2(cr, ci);
-                        const int t0 = c * Lc, len = max(0, min(N, t0 + Lc) - t0);
-                        const float mag = expf(-(float)len * a_);
-                        float sn, cs;
-                        sincosf((float)len * b_, &sn, &cs);
-                        const float pr = mag * cs, pi = mag * sn;
-                        const float2 e = endst[c * items + it];
-                        const float nr = pr * cr - pi * ci + e.x;
-                        const float ni = pr * ci + pi * cr + e.y;
-                        cr = nr;
-                        ci = ni;
-                    }
-                }
+                lru_carries(nu, ph, dh, items, nch, Lc, N, endst, carry);
                 __syncthreads();
                 // phase 3: h_t += lambda^(t - t0 + 1) carry
                 for (int w = tid; w < items * nch; w += kThreads) {
@@ -165,19 +319,59 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
                     }
                 }
             }
-            // seeds: y = D x, and the GLU biases
-            for (int e = tid; e < d * cols; e += kThreads) Y[e] = Dv[e / cols] * X[e];
-            for (int e = tid; e < 2 * d * cols; e += kThreads) GL[e] = bg[e / cols];
+            }
+            // seeds: y = D x, and the GLU biases (loads in batches of kB, then the stores)
+            for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
+                float xv[kB], dv[kB];
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    xv[k] = (e < d * cols) ? X[e] : 0.0f;
+                    dv[k] = (e < d * cols) ? Dv[e / cols] : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    if (e < d * cols) Y[e] = dv[k] * xv[k];
+                }
+            }
+            for (int e0 = tid; e0 < 2 * d * cols; e0 += kB * kThreads) {
+                float bv[kB];
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    bv[k] = (e < 2 * d * cols) ? bg[e / cols] : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    if (e < 2 * d * cols) GL[e] = bv[k];
+                }
+            }
             __syncthreads();
-            // y += Re(C h) = C_re h_re + C_im (-h_im)
-            gemm(d, cols, 2 * dh, MA{Cm, 2 * dh, 1}, MB{U, cols, 1}, MC{Y, cols, 1}, true);
+            // y += Re(C h) = C_re h_re + C_im (-h_im), one pass per half of C's columns (the
+            // two passes give each output element to the same lane, in this order)
+            gemm_lru(d, cols, dh, Cm, 2 * dh, U, cols, Y, cols, true);
+            gemm_lru(d, cols, dh, Cm + dh, 2 * dh, U + (int64_t)dh * cols, cols, Y, cols, true);
             __syncthreads();
-            gemm(2 * d, cols, d, MA{Wg, d, 1}, MB{Y, cols, 1}, MC{GL, cols, 1}, true);
+            gemm_lru(2 * d, cols, d, Wg, d, Y, cols, GL, cols, true);
             __syncthreads();
-            // GLU and the residual (from the second layer on)
-            for (int e = tid; e < d * cols; e += kThreads) {
-                const float v = GL[e] * sigm(GL[e + (int64_t)d * cols]);
-                X[e] = (l >= 1) ? X[e] + v : v;
+            // GLU and the residual (from the second layer on), loads in batches of kB
+            for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
+                float gv[kB], gg[kB], xv[kB];
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    const bool in = e < d * cols;
+                    gv[k] = in ? GL[e] : 0.0f;
+                    gg[k] = in ? GL[e + (int64_t)d * cols] : 0.0f;
+                    xv[k] = (in && l >= 1) ? X[e] : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < kB; ++k) {
+                    const int e = e0 + k * kThreads;
+                    if (e < d * cols) X[e] = xv[k] + gv[k] * sigm(gg[k]);
+                }
             }
             __syncthreads();
         }
