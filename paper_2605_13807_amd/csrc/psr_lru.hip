@@ -60,11 +60,12 @@ __device__ inline float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(
 // loads before the current tile's MFMAs.  Lane layout of the FP32 16x16x4 MFMA: a
 // lane holds A(m0 + lane%16, 4j + lane/16), B(4j + lane/16, n0 + lane%16) and
 // outputs rows m0 + 4 (lane/16) + i of column n0 + lane%16.  M is a multiple of 16;
-// N is masked (columns past N read column N - 1 and are not stored).  Called by
-// the whole workgroup; no barrier inside.
+// N is masked (columns past N read column N - 1 and are not stored).  With dseed,
+// C = dseed[row] xseed(row, n) + A B (xseed with C's strides).  Called by the whole
+// workgroup; no barrier inside.
 constexpr int kKQ = 16;
 __device__ inline void gemm_ws(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
-                               int ldc, bool acc_in) {
+                               int ldc, bool acc_in, const float* dseed = nullptr, const float* xseed = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int kq = lane >> 4, r16 = lane & 15;
     const int tm = M >> 4, tn = (N + 15) >> 4, KQ = K >> 2;
@@ -102,12 +103,74 @@ __device__ inline void gemm_ws(int M, int N, int K, const float* A, int lda, con
             if (n < N) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    float* cp = C + (int64_t)(m0 + 4 * kq + i) * ldc + n;
-                    *cp = acc_in ? *cp + acc[i] : acc[i];
+                    const int row = m0 + 4 * kq + i;
+                    float* cp = C + (int64_t)row * ldc + n;
+                    if (dseed)   // C = dseed[row] * xseed(row, n) + A B
+                        *cp = fmaf(dseed[row], xseed[(int64_t)row * ldc + n], acc[i]);
+                    else
+                        *cp = acc_in ? *cp + acc[i] : acc[i];
                 }
             }
 #pragma unroll
             for (int j = 0; j < kKQ; ++j) bc[j] = bn[j];
+        }
+    }
+}
+
+// GLU fused with its projections and the residual, for d <= 4 kKQ:
+//   X(m, n) = [res] X(m, n) + (W_a y + b_a)(m, n) sigmoid(W_g y + b_g)(m, n),
+// W = [W_a; W_g] ([2 d][d]), b = [b_a; b_g], y = Y ([d][ldb]).  A wave computes the value
+// and the gate tile of the same 16 rows, so the gate is applied in registers (no B
+// prefetch here: it measured no faster and spilled registers).  X is only touched at
+// the element each lane writes (Y is the B operand).  Whole workgroup.
+__device__ inline void gemm_glu_ws(int d, int N, const float* W, const float* b, const float* Y, int ldb, float* X,
+                                   int ldc, bool res) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int kq = lane >> 4, r16 = lane & 15;
+    const int tm = d >> 4, tn = (N + 15) >> 4, KQ = d >> 2;
+    int mt0 = wave, mstep = nw, nt0 = 0, nstep = 1;
+    if (tm < nw) {
+        const int wpm = nw / tm;
+        mt0 = wave / wpm;
+        nt0 = wave % wpm;
+        nstep = wpm;
+    }
+    for (int mt = mt0; mt < tm; mt += mstep) {
+        const int m0 = mt << 4;
+        float av[kKQ], ag[kKQ];
+        const float* pv = W + (int64_t)(m0 + r16) * d + kq;
+        const float* pg = pv + (int64_t)d * d;
+#pragma unroll
+        for (int j = 0; j < kKQ; ++j) {
+            av[j] = (j < KQ) ? pv[4 * j] : 0.0f;
+            ag[j] = (j < KQ) ? pg[4 * j] : 0.0f;
+        }
+        float bc[kKQ];
+        auto loadb = [&](int nt, float* bb) {
+            const int n = min((nt << 4) + r16, N - 1);
+            const float* bp = Y + (int64_t)kq * ldb + n;
+#pragma unroll
+            for (int j = 0; j < kKQ; ++j) bb[j] = (j < KQ) ? bp[(int64_t)4 * j * ldb] : 0.0f;
+        };
+        for (int nt = nt0; nt < tn; nt += nstep) {
+            loadb(nt, bc);
+            f32x4 accv = {0.f, 0.f, 0.f, 0.f}, accg = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < kKQ; ++j)
+                if (j < KQ) {
+                    accv = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bc[j], accv, 0, 0, 0);
+                    accg = __builtin_amdgcn_mfma_f32_16x16x4f32(ag[j], bc[j], accg, 0, 0, 0);
+                }
+            const int n = (nt << 4) + r16;
+            if (n < N) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = m0 + 4 * kq + i;
+                    float* xp = X + (int64_t)row * ldc + n;
+                    const float v = (accv[i] + b[row]) * sigm(accg[i] + b[d + row]);
+                    *xp = res ? *xp + v : v;
+                }
+            }
         }
     }
 }
@@ -320,60 +383,72 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
                 }
             }
             }
-            // seeds: y = D x, and the GLU biases (loads in batches of kB, then the stores)
-            for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
-                float xv[kB], dv[kB];
+            if (d <= 4 * kKQ && dh <= 4 * kKQ) {
+                // y = D x + C_re h_re + C_im (-h_im): the seed in the first pass's epilogue,
+                // the second pass accumulating (both give an element to the same lane);
+                // the barrier orders the scan's stores of h before the passes read them
+                __syncthreads();
+                gemm_ws(d, cols, dh, Cm, 2 * dh, U, cols, Y, cols, false, Dv, X);
+                gemm_ws(d, cols, dh, Cm + dh, 2 * dh, U + (int64_t)dh * cols, cols, Y, cols, true);
+                __syncthreads();
+                gemm_glu_ws(d, cols, Wg, bg, Y, cols, X, cols, l >= 1);
+                __syncthreads();
+            } else {
+                // seeds: y = D x, and the GLU biases (loads in batches of kB, then the stores)
+                for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
+                    float xv[kB], dv[kB];
 #pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    xv[k] = (e < d * cols) ? X[e] : 0.0f;
-                    dv[k] = (e < d * cols) ? Dv[e / cols] : 0.0f;
-                }
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        xv[k] = (e < d * cols) ? X[e] : 0.0f;
+                        dv[k] = (e < d * cols) ? Dv[e / cols] : 0.0f;
+                    }
 #pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    if (e < d * cols) Y[e] = dv[k] * xv[k];
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        if (e < d * cols) Y[e] = dv[k] * xv[k];
+                    }
                 }
+                for (int e0 = tid; e0 < 2 * d * cols; e0 += kB * kThreads) {
+                    float bv[kB];
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        bv[k] = (e < 2 * d * cols) ? bg[e / cols] : 0.0f;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        if (e < 2 * d * cols) GL[e] = bv[k];
+                    }
+                }
+                __syncthreads();
+                // y += Re(C h) = C_re h_re + C_im (-h_im), one pass per half of C's columns (the
+                // two passes give each output element to the same lane, in this order)
+                gemm_lru(d, cols, dh, Cm, 2 * dh, U, cols, Y, cols, true);
+                gemm_lru(d, cols, dh, Cm + dh, 2 * dh, U + (int64_t)dh * cols, cols, Y, cols, true);
+                __syncthreads();
+                gemm_lru(2 * d, cols, d, Wg, d, Y, cols, GL, cols, true);
+                __syncthreads();
+                // GLU and the residual (from the second layer on), loads in batches of kB
+                for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
+                    float gv[kB], gg[kB], xv[kB];
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        const bool in = e < d * cols;
+                        gv[k] = in ? GL[e] : 0.0f;
+                        gg[k] = in ? GL[e + (int64_t)d * cols] : 0.0f;
+                        xv[k] = (in && l >= 1) ? X[e] : 0.0f;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kB; ++k) {
+                        const int e = e0 + k * kThreads;
+                        if (e < d * cols) X[e] = xv[k] + gv[k] * sigm(gg[k]);
+                    }
+                }
+                __syncthreads();
             }
-            for (int e0 = tid; e0 < 2 * d * cols; e0 += kB * kThreads) {
-                float bv[kB];
-#pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    bv[k] = (e < 2 * d * cols) ? bg[e / cols] : 0.0f;
-                }
-#pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    if (e < 2 * d * cols) GL[e] = bv[k];
-                }
-            }
-            __syncthreads();
-            // y += Re(C h) = C_re h_re + C_im (-h_im), one pass per half of C's columns (the
-            // two passes give each output element to the same lane, in this order)
-            gemm_lru(d, cols, dh, Cm, 2 * dh, U, cols, Y, cols, true);
-            gemm_lru(d, cols, dh, Cm + dh, 2 * dh, U + (int64_t)dh * cols, cols, Y, cols, true);
-            __syncthreads();
-            gemm_lru(2 * d, cols, d, Wg, d, Y, cols, GL, cols, true);
-            __syncthreads();
-            // GLU and the residual (from the second layer on), loads in batches of kB
-            for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
-                float gv[kB], gg[kB], xv[kB];
-#pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    const bool in = e < d * cols;
-                    gv[k] = in ? GL[e] : 0.0f;
-                    gg[k] = in ? GL[e + (int64_t)d * cols] : 0.0f;
-                    xv[k] = (in && l >= 1) ? X[e] : 0.0f;
-                }
-#pragma unroll
-                for (int k = 0; k < kB; ++k) {
-                    const int e = e0 + k * kThreads;
-                    if (e < d * cols) X[e] = xv[k] + gv[k] * sigm(gg[k]);
-                }
-            }
-            __syncthreads();
         }
         // head: logit(0) - logit(1) per column; log p of the own spin into GL's first row
         for (int col = tid; col < cols; col += kThreads) {

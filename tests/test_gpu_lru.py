@@ -44,6 +44,7 @@ def _tol(ref):
 LRU_CASES = [
     # n, nl, d, dh, B
     (16, 1, 16, 32, 33),       # 16 chains per group, one scan chunk per chain
+    (16, 1, 32, 32, 33),       # the same with d = d_h: the output map must wait for every scan store
     (6, 3, 64, 64, 100),       # the Table I model at N = 6; ragged last group
     (100, 2, 32, 16, 7),       # 2 chains per group, 16 chunks of 7 sites (ragged last chunk)
     (256, 3, 64, 64, 5),       # the Table I model at N = 256: one chain per group, 8 chunks
