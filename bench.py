@@ -283,6 +283,19 @@ def main() -> int:
                "peak": PEAK["fp32_tflops"], "unit": "TFLOP/s", "frac": round(tfl / PEAK["fp32_tflops"], 4)}
         print(f"# lru: {ms_call:.2f} ms per {BL} chains of {nL}", file=sys.stderr, flush=True)
         del wsL, seqL
+        # the whole E_loc call on the same 1024 samples (enumeration, both forwards, FP64 combine)
+        HL = P.Hamiltonian(P.TFIM, nL, 1, J=1.0, h=1.0)
+        P.lru_local_energy(mL, thL, HL, sL)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            P.lru_local_energy(mL, thL, HL, sL)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_e = e0.elapsed_time(e1) / 3
+        lru["eloc_ms_per_call"] = round(ms_e, 3)
+        lru["eloc_site_evals_per_s"] = (nsL * (nL + 1)) * nL / (ms_e / 1000.0)
+        print(f"# lru E_loc: {ms_e:.2f} ms per {nsL} samples", file=sys.stderr, flush=True)
 
     # CPU oracle baseline on a bounded sample, and the E_loc error on that sample
     cpu = None

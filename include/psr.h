@@ -251,6 +251,27 @@ int64_t psr_lru_workspace_bytes(const psr_lru_desc* m, int64_t batch);
 int psr_lru_logpsi(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B,
                    float* logpsi, float* logp_site, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Local energies of a batch of chains under the 1D LRU ansatz (the E_loc of
+ * Sec. III.B: E_loc(sigma) = sum_sigma' H(sigma, sigma') psi(sigma') / psi(sigma)),
+ * with their FP64 mean and variance (1/B).  H is PSR_TFIM or PSR_HEISENBERG on an
+ * open chain (lx = n, ly = 1).  The connected configurations are enumerated in the
+ * order of psr_connected, written out in full, and evaluated by the kernel of
+ * psr_lru_logpsi; the ratio sum runs in FP64.
+ *   theta   device, float[P];  spins  device, int8[B][n] in {0, 1}
+ *   eloc    device, double[B]  (out);  stats  device, double[2] = (mean, variance) (out)
+ *   logpsi  device, float[B] or NULL (out) log psi of the samples
+ *   ws      device workspace of psr_lru_eloc_workspace_bytes(m, H, B) bytes, owned by the caller
+ *           (it holds every connected configuration: B * max_connected * n bytes among the rest)
+ * Errors: PSR_EINVAL (descriptors, lattice mismatch, NULL pointer), PSR_EUNSUPPORTED
+ * (periodic boundaries), PSR_ENOMEM (workspace too small), PSR_EDEVICE (launch).
+ * Queued on `stream`; the call does not wait for it.
+ */
+int64_t psr_lru_eloc_workspace_bytes(const psr_lru_desc* m, const psr_hamiltonian* H, int64_t batch);
+int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_hamiltonian* H, const int8_t* spins,
+                         int64_t B, double* eloc, double* stats, float* logpsi, void* ws, size_t ws_bytes,
+                         void* stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Timing of the forward (log psi) kernel, for measurement tools.  After

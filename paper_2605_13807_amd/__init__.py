@@ -143,6 +143,10 @@ def lib() -> ctypes.CDLL:
         L.psr_lru_workspace_bytes.restype = i64
         L.psr_lru_logpsi.argtypes = [P(_LruDesc), vp, vp, i64, vp, vp, vp, sz, vp]
         L.psr_lru_logpsi.restype = ctypes.c_int
+        L.psr_lru_eloc_workspace_bytes.argtypes = [P(_LruDesc), P(_HamDesc), i64]
+        L.psr_lru_eloc_workspace_bytes.restype = i64
+        L.psr_lru_local_energy.argtypes = [P(_LruDesc), vp, P(_HamDesc), vp, i64, vp, vp, vp, vp, sz, vp]
+        L.psr_lru_local_energy.restype = ctypes.c_int
         L.psr_check_spins.argtypes = [vp, i64, vp]
         L.psr_check_spins.restype = ctypes.c_int
         L.psr_timing_begin.argtypes = []
@@ -248,6 +252,25 @@ def lru_logpsi(m: LruModel, theta: torch.Tensor, spins: torch.Tensor, site_logp:
     _check(lib().psr_lru_logpsi(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps), _ptr(ws),
                                 ws.numel(), _stream(spins.device)))
     return (out, lps) if site_logp else out
+
+
+def lru_local_energy(m: LruModel, theta: torch.Tensor, h: Hamiltonian, spins: torch.Tensor,
+                     ws: torch.Tensor | None = None):
+    """(E_loc [B] float64, stats [2] float64 = (mean, variance), log psi [B] float32) under the 1D LRU."""
+    theta = _dev(theta, torch.float32, "theta")
+    spins = _dev(spins, torch.int8, "spins")
+    B = spins.shape[0]
+    dev = spins.device
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    st = torch.zeros(2, dtype=torch.float64, device=dev)
+    lp = torch.empty(B, dtype=torch.float32, device=dev)
+    if ws is None:
+        n = lib().psr_lru_eloc_workspace_bytes(ctypes.byref(m.c()), ctypes.byref(h.c()), B)
+        _check(int(n) if n < 0 else 0)
+        ws = torch.empty(max(1, int(n)), dtype=torch.uint8, device=dev)
+    _check(lib().psr_lru_local_energy(ctypes.byref(m.c()), _ptr(theta), ctypes.byref(h.c()), _ptr(spins), B, _ptr(e),
+                                      _ptr(st), _ptr(lp), _ptr(ws), ws.numel(), _stream(dev)))
+    return e, st, lp
 
 
 def connected(h: Hamiltonian, spins: torch.Tensor, max_conn: int | None = None, configs: bool = False):

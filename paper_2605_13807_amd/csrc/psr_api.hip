@@ -645,6 +645,101 @@ int psr_lru_logpsi(const psr_lru_desc* m, const float* theta, const int8_t* spin
     return ok();
 }
 
+// workspace of psr_lru_local_energy: connected slots, their configurations, both log psi
+// arrays and the LRU kernel's scratch for the larger of its two launches
+struct LruElocWs {
+    int32_t* n_conn;
+    float* diag;
+    uint32_t* desc;
+    float* mel;
+    int8_t* conn;
+    float* lps;
+    float* lpc;
+    float* scratch;
+};
+
+static int64_t carve_lru_eloc(const LruGeom& g, int64_t B, int64_t mc, void* base, LruElocWs* w) {
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o += align256(bytes);
+        return base ? static_cast<char*>(base) + at : nullptr;
+    };
+    const int64_t M = B * mc;
+    w->n_conn = reinterpret_cast<int32_t*>(take(B * 4));
+    w->diag = reinterpret_cast<float*>(take(B * 4));
+    w->desc = reinterpret_cast<uint32_t*>(take(M * 8));
+    w->mel = reinterpret_cast<float*>(take(M * 4));
+    w->conn = reinterpret_cast<int8_t*>(take(M * g.n));
+    w->lps = reinterpret_cast<float*>(take(B * 4));
+    w->lpc = reinterpret_cast<float*>(take(M * 4));
+    const int64_t sc = lru_workspace_floats(g, M > B ? M : B);
+    w->scratch = reinterpret_cast<float*>(take(sc * 4));
+    return o;
+}
+
+static int check_lru_ham(const LruGeom& g, const psr_hamiltonian* H, Ham* h) {
+    int r = check_ham(H, h);
+    if (r) return r;
+    if (h->ly != 1 || h->lx != g.n)
+        return fail(PSR_EINVAL, "Hamiltonian lattice %d x %d is not the model's chain of %d sites", h->lx, h->ly, g.n);
+    return PSR_OK;
+}
+
+int64_t psr_lru_eloc_workspace_bytes(const psr_lru_desc* m, const psr_hamiltonian* H, int64_t batch) {
+    LruGeom g;
+    int r = check_lru(m, &g);
+    if (r) return r;
+    Ham h;
+    if ((r = check_lru_ham(g, H, &h))) return r;
+    if (batch < 0) return fail(PSR_EINVAL, "negative batch");
+    ok();
+    LruElocWs w;
+    return carve_lru_eloc(g, batch, ham_max_connected(h), nullptr, &w);
+}
+
+int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_hamiltonian* H, const int8_t* spins,
+                         int64_t B, double* eloc, double* stats, float* logpsi, void* ws, size_t ws_bytes,
+                         void* stream) {
+    LruGeom g;
+    int r = check_lru(m, &g);
+    if (r) return r;
+    Ham h;
+    if ((r = check_lru_ham(g, H, &h))) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !spins || !eloc || !stats) return fail(PSR_EINVAL, "theta, spins, eloc and stats must not be NULL");
+    const int64_t mc = ham_max_connected(h);
+    LruElocWs w;
+    const int64_t need = carve_lru_eloc(g, B, mc, nullptr, &w);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    carve_lru_eloc(g, B, mc, ws, &w);
+    hipStream_t st = as_stream(stream);
+    const int64_t M = B * mc;
+    if ((r = dev_check(launch_conn_count(h, spins, B, w.n_conn, w.diag, st), "connected count"))) return r;
+    if ((r = dev_check(launch_conn_write(h, spins, B, nullptr, mc, w.desc, w.mel, st), "connected write"))) return r;
+    if ((r = dev_check(launch_conn_expand(spins, g.n, B, mc, w.n_conn, w.desc, w.conn, st), "connected expand")))
+        return r;
+    // slots past a sample's count hold unwritten bytes: the kernel reads only their low
+    // bit and the combine never reads their log psi
+    for (int pass = 0; pass < 2; ++pass) {
+        hipEvent_t stop;
+        timing_before(st, &stop);
+        const int e = pass == 0 ? launch_lru_logpsi(g, theta, spins, B, w.lps, nullptr, w.scratch, st)
+                                : launch_lru_logpsi(g, theta, w.conn, M, w.lpc, nullptr, w.scratch, st);
+        if (stop && hipEventRecord(stop, st) != hipSuccess) --g_tm.used;
+        if ((r = dev_check(e, "LRU forward"))) return r;
+    }
+    if ((r = dev_check(launch_lru_eloc_combine(B, mc, w.n_conn, w.diag, w.mel, w.lpc, w.lps, eloc, st), "E_loc")))
+        return r;
+    if ((r = dev_check(launch_stats(eloc, B, stats, st), "stats"))) return r;
+    if (logpsi && (r = dev_check(hipMemcpyAsync(logpsi, w.lps, B * sizeof(float), hipMemcpyDeviceToDevice, st),
+                                 "log psi copy")))
+        return r;
+    return ok();
+}
+
 int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream) {
     if (n_values < 0) return fail(PSR_EINVAL, "negative size");
     if (n_values == 0) return ok();

@@ -151,5 +151,8 @@ int64_t lru_param_count(const LruGeom& g);
 int64_t lru_workspace_floats(const LruGeom& g, int64_t B);
 int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
                       float* logp_site, float* scratch, hipStream_t st);
+// E_loc from per-sample connected slots (s * max_conn + k) and the two log psi arrays
+int launch_lru_eloc_combine(int64_t B, int64_t max_conn, const int32_t* n_conn, const float* diag, const float* mel,
+                            const float* lpc, const float* lps, double* eloc, hipStream_t st);
 
 }  // namespace psr

@@ -484,6 +484,25 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
     }
 }
 
+// E_loc(s) = diag(s) + sum_{k < n_conn(s)} mel(s, k) exp(log psi(sigma'_k) - log psi(sigma_s))
+// with the connected entries in per-sample slots (s * max_conn + k).  One wave per
+// sample, FP64 accumulation in a fixed order.
+__global__ void lru_eloc_kernel(int64_t B, int64_t max_conn, const int32_t* __restrict__ n_conn,
+                                const float* __restrict__ diag, const float* __restrict__ mel,
+                                const float* __restrict__ lpc, const float* __restrict__ lps,
+                                double* __restrict__ eloc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (s >= B) return;
+    const int64_t base = s * max_conn;
+    const int nc = n_conn[s];
+    const double l0 = (double)lps[s];
+    double acc = 0.0;
+    for (int k = lane; k < nc; k += 64) acc += (double)mel[base + k] * exp((double)lpc[base + k] - l0);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) eloc[s] = (double)diag[s] + acc;
+}
+
 int lru_seqs_per_group(const LruGeom& g) { return g.n >= kColTarget ? 1 : kColTarget / g.n; }
 
 int64_t lru_per_wg_floats(const LruGeom& g) {
@@ -511,6 +530,13 @@ int64_t lru_param_count(const LruGeom& g) {
 int64_t lru_workspace_floats(const LruGeom& g, int64_t B) {
     if (B <= 0) return 0;
     return lru_grid(g, B) * lru_per_wg_floats(g);
+}
+
+int launch_lru_eloc_combine(int64_t B, int64_t max_conn, const int32_t* n_conn, const float* diag, const float* mel,
+                            const float* lpc, const float* lps, double* eloc, hipStream_t st) {
+    if (B == 0) return 0;
+    lru_eloc_kernel<<<(unsigned)((B + 3) / 4), 256, 0, st>>>(B, max_conn, n_conn, diag, mel, lpc, lps, eloc);
+    return (int)hipGetLastError();
 }
 
 int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,

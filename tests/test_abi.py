@@ -154,3 +154,23 @@ def test_lru_layout_and_host_checks(P):
     assert L.psr_lru_logpsi(ctypes.byref(m), fake, fake, -1, fake, None, fake, 1 << 40, None) == -1
     assert L.psr_lru_logpsi(ctypes.byref(m), None, None, 0, None, None, None, 0, None) == 0
     assert L.psr_last_error() == b""
+
+
+def test_lru_local_energy_host_checks(P):
+    L = P.lib()
+    fake = ctypes.c_void_p(16)
+    m = P.LruModel(16, 2, 32, 32).c()
+    h_ok = P.Hamiltonian(P.TFIM, 16, 1).c()
+    assert L.psr_lru_eloc_workspace_bytes(ctypes.byref(m), ctypes.byref(h_ok), 10) > 0
+    assert L.psr_lru_eloc_workspace_bytes(ctypes.byref(m), ctypes.byref(h_ok), -1) == -1
+    for bad in (P.Hamiltonian(P.TFIM, 15, 1), P.Hamiltonian(P.HEISENBERG, 8, 2), P.Hamiltonian(P.TFIM, 16, 1, pbc=True)):
+        code = L.psr_lru_local_energy(ctypes.byref(m), fake, ctypes.byref(bad.c()), fake, 4, fake, fake, None, fake,
+                                      1 << 40, None)
+        assert code in (-1, -2), bad
+    # NULL outputs, workspace too small, empty batch
+    assert L.psr_lru_local_energy(ctypes.byref(m), fake, ctypes.byref(h_ok), fake, 4, None, fake, None, fake, 1 << 40,
+                                  None) == -1
+    assert L.psr_lru_local_energy(ctypes.byref(m), fake, ctypes.byref(h_ok), fake, 4, fake, fake, None, fake, 64,
+                                  None) == -3
+    assert L.psr_lru_local_energy(ctypes.byref(m), None, ctypes.byref(h_ok), None, 0, None, None, None, None, 0,
+                                  None) == 0

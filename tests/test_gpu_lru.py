@@ -119,3 +119,34 @@ def test_lru_full_eloc_batch_sampled(P):
     # the same chains evaluated alone, in a small launch: identical values
     alone = P.lru_logpsi(m, torch.from_numpy(th).cuda(), seqs[picks].contiguous())
     assert torch.equal(alone, lp[picks])
+
+
+ELOC_CASES = [
+    # kind, n, nl, d, dh, B
+    ("tfim", 10, 2, 16, 16, 20),
+    ("heisenberg", 9, 1, 32, 32, 15),
+    ("tfim", 64, 3, 64, 64, 6),
+]
+
+
+@pytest.mark.parametrize("kind,n,nl,d,dh,B", ELOC_CASES)
+def test_lru_local_energy_parity(P, kind, n, nl, d, dh, B):
+    """E_loc against the oracle's E_loc with the LRU oracle's log psi (Sec. III.B), and the
+    FP64 statistics of exactly the returned values."""
+    from oracle import hamiltonian as OH
+    print(f"LRU E_loc case {kind} n={n} nl={nl} d={d} dh={dh} B={B}", flush=True)
+    m, om, th, s = _case(P, n, nl, d, dh, B, seed=5 * n + d)
+    if kind == "tfim":
+        H, oh = P.Hamiltonian(P.TFIM, n, 1, J=1.0, h=1.0), OH.Hamiltonian("tfim", n, 1, J=1.0, h=1.0)
+    else:
+        H, oh = P.Hamiltonian(P.HEISENBERG, n, 1, J=1.0), OH.Hamiltonian("heisenberg", n, 1, J=1.0)
+    th_d = torch.from_numpy(th).cuda()
+    e, st, lp = P.lru_local_energy(m, th_d, H, torch.from_numpy(s).cuda())
+    e, st = e.cpu().numpy(), st.cpu().numpy()
+    ref = OH.local_energy(lambda c: OL.logpsi(th, c, om), oh, s)
+    rel = np.abs(e - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  max rel E_loc err {rel:.3e}; mean {st[0]:.6f}")
+    assert rel <= 1e-4
+    assert abs(st[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
+    assert abs(st[1] - e.var()) <= 1e-10 * max(1.0, e.var())
+    assert torch.equal(lp, P.lru_logpsi(m, th_d, torch.from_numpy(s).cuda()))
