@@ -36,6 +36,7 @@ constexpr int kThreads = 512;
 constexpr int kColTarget = 256;     // columns per group for short chains
 constexpr int kR = 32;              // longest scan chunk held in registers
 constexpr int kB = 8;               // elementwise loops: loads in flight per thread
+constexpr int kXYLds = 2 * 64 * 256;  // floats of LDS for X and Y (128 KB)
 constexpr int64_t kMaxGroupsInFlight = 1024;
 
 struct LruArgs {
@@ -209,15 +210,25 @@ __device__ inline void lru_carries(const float* nu, const float* ph, int dh, int
     }
 }
 
+// XY_LDS: the layer input X and the output map's result Y live in LDS (the fused
+// path for d, d_h <= 4 kKQ with 2 d S N <= kXYLds); otherwise in the workspace.
+template <bool XY_LDS>
 __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
     const LruGeom& G = a.g;
     const int N = G.n, d = G.d, dh = G.dh, nl = G.nl, S = a.S;
     const int cols = S * N;
     const int tid = threadIdx.x;
-    float* X = a.scratch + (int64_t)blockIdx.x * a.per_wg;   // [d][cols]
-    float* U = X + (int64_t)d * cols;                          // [2 dh][cols]
-    float* Y = U + (int64_t)2 * dh * cols;                     // [d][cols]
-    float* GL = Y + (int64_t)d * cols;                         // [2 d][cols]
+    float* Xg = a.scratch + (int64_t)blockIdx.x * a.per_wg;  // [d][cols]
+    float* U = Xg + (int64_t)d * cols;                         // [2 dh][cols]
+    float* Yg = U + (int64_t)2 * dh * cols;                    // [d][cols]
+    float* GL = Yg + (int64_t)d * cols;                        // [2 d][cols]
+    float* X = Xg;
+    float* Y = Yg;
+    if constexpr (XY_LDS) {
+        __shared__ float xy[kXYLds];
+        X = xy;
+        Y = xy + d * cols;
+    }
     const float* th = a.theta;
     const int64_t lstride = lru_layer_floats(G);
     const float* Wo = th + (int64_t)2 * d + nl * lstride;
@@ -383,7 +394,7 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
                 }
             }
             }
-            if (d <= 4 * kKQ && dh <= 4 * kKQ) {
+            if (XY_LDS || (d <= 4 * kKQ && dh <= 4 * kKQ)) {
                 // y = D x + C_re h_re + C_im (-h_im): the seed in the first pass's epilogue,
                 // the second pass accumulating (both give an element to the same lane);
                 // the barrier orders the scan's stores of h before the passes read them
@@ -393,7 +404,7 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
                 __syncthreads();
                 gemm_glu_ws(d, cols, Wg, bg, Y, cols, X, cols, l >= 1);
                 __syncthreads();
-            } else {
+            } else if constexpr (!XY_LDS) {
                 // seeds: y = D x, and the GLU biases (loads in batches of kB, then the stores)
                 for (int e0 = tid; e0 < d * cols; e0 += kB * kThreads) {
                     float xv[kB], dv[kB];
@@ -553,7 +564,11 @@ int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins,
     a.logp_site = logp_site;
     a.scratch = scratch;
     a.per_wg = lru_per_wg_floats(g);
-    hipLaunchKernelGGL(lru_kernel, dim3((unsigned)lru_grid(g, B)), dim3(kThreads), 0, st, a);
+    const bool xy_lds = g.d <= 4 * kKQ && g.dh <= 4 * kKQ && (int64_t)2 * g.d * a.S * g.n <= kXYLds;
+    if (xy_lds)
+        hipLaunchKernelGGL(lru_kernel<true>, dim3((unsigned)lru_grid(g, B)), dim3(kThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(lru_kernel<false>, dim3((unsigned)lru_grid(g, B)), dim3(kThreads), 0, st, a);
     return (int)hipGetLastError();
 }
 
