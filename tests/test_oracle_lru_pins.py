@@ -147,3 +147,75 @@ def test_residual_from_the_second_layer_only():
     lse = math.log(math.exp(bo[0]) + math.exp(bo[1]))
     want = 0.5 * (bo[s.astype(int)] - lse).sum(axis=1)
     np.testing.assert_allclose(OL.logpsi(th1, s, m1), want, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: each plausible error in the oracle's layer is rejected by a pin
+# ---------------------------------------------------------------------------
+
+def _faulty_layer(kind):
+    def layer(x, p, l, return_h=False):
+        dh = p[f"nu{l}"].shape[0]
+        Bc = p[f"B{l}"][:dh] + 1j * p[f"B{l}"][dh:]
+        Cc = p[f"C{l}"][:, :dh] + 1j * p[f"C{l}"][:, dh:]
+        lm = OL.lam(p[f"nu{l}"], p[f"theta{l}"])
+        v = np.exp(p[f"gamma{l}"]) * (x @ Bc.T)
+        h = np.zeros(v.shape, dtype=np.complex128)
+        st = np.zeros(v[:, 0].shape, dtype=np.complex128)
+        for t in range(x.shape[1]):
+            st = lm * st + v[:, t]
+            h[:, t] = st
+        y = (h @ Cc.T).real + (0.0 if kind == "no_D" else p[f"D{l}"] * x)
+        d = x.shape[2]
+        W, b = p[f"Wglu{l}"], p[f"bglu{l}"]
+        if kind == "swapped_glu":
+            g = (y @ W[d:].T + b[d:]) * OL.sigmoid(y @ W[:d].T + b[:d])
+        else:
+            g = (y @ W[:d].T + b[:d]) * OL.sigmoid(y @ W[d:].T + b[d:])
+        res = (l >= 0) if kind == "residual_everywhere" else (l >= 1)
+        xn = g + (x if res else 0.0)
+        return (xn, h) if return_h else xn
+    return layer
+
+
+@pytest.mark.parametrize("kind", ["no_D", "swapped_glu", "residual_everywhere"])
+def test_planted_layer_mistakes_are_rejected(monkeypatch, kind):
+    monkeypatch.setattr(OL, "layer", _faulty_layer(kind))
+    caught = 0
+    for pin in (test_hand_derived_three_site_model, test_residual_from_the_second_layer_only):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, kind
+
+
+def test_planted_conjugate_propagator_is_rejected(monkeypatch):
+    orig = OL.lam
+    monkeypatch.setattr(OL, "lam", lambda nu, th: np.conj(orig(nu, th)))
+    with pytest.raises(AssertionError):
+        test_propagator_at_a_hand_chosen_point()
+    with pytest.raises(AssertionError):
+        test_hand_derived_three_site_model()
+
+
+def test_planted_missing_input_shift_is_rejected(monkeypatch):
+    """Feeding E[:, sigma_t] instead of E[:, sigma_{t-1}] makes site t see its own spin:
+    the distribution is no longer normalised."""
+    orig_site_logp = OL.site_logp
+
+    def site_logp(theta, spins, m):
+        p = OL.unpack(theta, m)
+        s = np.asarray(spins).astype(np.int64)
+        x = p["E"].T[s]
+        for l in range(m.n_layers):
+            x = OL.layer(x, p, l)
+        logits = x @ p["W_o"].T + p["b_o"]
+        mx = logits.max(axis=2, keepdims=True)
+        lse = mx[..., 0] + np.log(np.exp(logits - mx).sum(axis=2))
+        return np.take_along_axis(logits, s[..., None], axis=2)[..., 0] - lse
+
+    monkeypatch.setattr(OL, "site_logp", site_logp)
+    with pytest.raises(AssertionError):
+        test_normalised_over_all_configurations(2, 8, 4)
+    monkeypatch.setattr(OL, "site_logp", orig_site_logp)
