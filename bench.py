@@ -264,14 +264,17 @@ def main() -> int:
         wsL = torch.empty(P.lru_workspace_bytes(mL, BL), dtype=torch.uint8, device=dev)
         P.lru_logpsi(mL, thL, seqL, ws=wsL)
         torch.cuda.synchronize()
-        reps = 5
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        # each call timed on its own (events around it, then a synchronisation), as it runs
+        # inside E_loc; calls queued back to back measured up to 28 % slower per launch
+        reps, ms_calls = 5, []
         for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             P.lru_logpsi(mL, thL, seqL, ws=wsL)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_call = e0.elapsed_time(e1) / reps
+            e1.record()
+            torch.cuda.synchronize()
+            ms_calls.append(e0.elapsed_time(e1))
+        ms_call = sum(ms_calls) / reps
         fl = lru_flops_per_site(nlL, dL, dhL)
         tfl = fl * nL * BL / (ms_call / 1000.0) / 1e12
         lru = {"kernel": "lru_kernel",
@@ -287,6 +290,7 @@ def main() -> int:
         HL = P.Hamiltonian(P.TFIM, nL, 1, J=1.0, h=1.0)
         P.lru_local_energy(mL, thL, HL, sL)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(3):
             P.lru_local_energy(mL, thL, HL, sL)
