@@ -40,7 +40,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define PSR_OK            0
 #define PSR_EINVAL       -1   /* invalid argument */
-#define PSR_EUNSUPPORTED -2   /* valid request that this build does not support */
+#define PSR_EUNSUPPORTED -2   /* valid request that this library does not support */
 #define PSR_ENOMEM       -3   /* workspace too small or allocation failed */
 #define PSR_EDEVICE      -4   /* HIP runtime error */
 #define PSR_ECAPACITY    -5   /* max_conn smaller than a sample's connected count */

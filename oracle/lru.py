@@ -18,7 +18,7 @@ Readings where the paper leaves a choice:
     two-way softmax on x^(n_layers)_t, as for the 2D model; psi = sqrt(p).
   * GLU (Shazeer) has its own value and gate projections with biases.
   With these shapes 3 layers at d = d_h = 64 have 75,138 parameters against the
-  paper's "around 75,000" (Table I caption).
+  paper's figure of about 75,000 (Table I caption).
 
 Parameter layout (flat float vector, matrices row-major, output index first):
   E[d][2]; per layer: nu[dh], theta[dh], gamma[dh], B[2 dh][d] (rows: Re then Im),

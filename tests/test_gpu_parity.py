@@ -1,6 +1,6 @@
 """GPU parity: the HIP library (through its C ABI) against the float64 oracle.
 
-Tolerances (derived in the design doc from the arithmetic of each path):
+Tolerances (derived from the arithmetic of each path):
   connected configurations, matrix elements, diagonal   bit-exact
   FP32 path   max |d log psi| <= 1e-5 + 1e-6 |log psi|  (about 16 float32 ulps of log psi)
   BF16 path   compared with the oracle's BF16 reading (projection operands

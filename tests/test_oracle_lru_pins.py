@@ -1,6 +1,6 @@
 """Pins of the 1D LRU oracle (Sec. II.B Eq. (lru), Sec. II.E, Table I) against facts outside itself.
 
-* the parameter count of the paper's 3-layer, d = d_h = 64 model ("around 75,000");
+* the parameter count of the paper's 3-layer, d = d_h = 64 model (about 75,000, Table I);
 * normalisation of the autoregressive distribution over all 2^N configurations;
 * causality: the conditional of site t sees sigma_<t only, and does see sigma_{t-1};
 * the propagator at a hand-chosen point (lambda = i/2 exactly);
