@@ -242,32 +242,9 @@ def _forward_chain(P, spins, m: Model, mode: str, keep_hidden: bool):
     return logp, hidden
 
 
-def round_bf16(x) -> np.ndarray:
-    """Round to the nearest bfloat16, ties to even, via float32; returned as float64."""
-    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool, bf16: bool = False):
+def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool):
     B, N = spins.shape
     lx, ly, d, nl = m.lx, m.ly, m.d, m.n_layers
-    R = round_bf16 if bf16 else (lambda v: v)
-    if bf16:
-        # the dense projections take bfloat16 operands: every weight matrix
-        # that multiplies a d-dimensional activation, and those activations
-        P = dict(P)
-        for l in range(nl):
-            du = 4 if l == 0 else d
-            wh = P[f"Wh{l}"].copy()
-            wh[:, du:] = R(wh[:, du:])
-            if l >= 1:
-                wh[:, :du] = R(wh[:, :du])
-                P[f"Wz{l}"] = R(P[f"Wz{l}"])
-                P[f"D{l}"] = R(P[f"D{l}"])
-            P[f"Wh{l}"] = wh
-            P[f"C{l}"] = R(P[f"C{l}"])
     frontier = [np.zeros((B, lx, d)) for _ in range(nl)]   # h^(l) of the previous row
     logp = np.empty((B, N))
     hidden = [np.zeros((B, N, d)) for _ in range(nl)] if keep_hidden else None
@@ -282,8 +259,8 @@ def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool, bf16: bool 
             u[:, i, 2:4] = _onehot_at(spins, lx, ly, vi, vj)
         h_below = None                                       # h^(l-1) of this row
         for l in range(nl):
-            hV = R(frontier[l])
-            ui = u if l == 0 else R(u)
+            hV = frontier[l]
+            ui = u
             z = expit(ui @ P[f"Wz{l}"].T + P[f"bz{l}"])
             ht = np.concatenate([ui, hV], axis=2) @ P[f"Wh{l}"].T + P[f"bh{l}"]
             # recurrence along the row in snake order, h_H = 0 at the row start
@@ -292,9 +269,9 @@ def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool, bf16: bool 
             hs = affine_seq(a, b) if mode == "seq" else affine_blelloch(a, b)
             h = np.empty_like(hs)
             h[:, cols] = hs
-            xt = R(h) @ P[f"C{l}"].T + ui @ P[f"D{l}"].T
+            xt = h @ P[f"C{l}"].T + ui @ P[f"D{l}"].T
             if l >= 2:
-                xt = xt + R(h_below)
+                xt = xt + h_below
             u = gelu(xt)
             frontier[l] = h
             h_below = h
@@ -306,20 +283,12 @@ def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool, bf16: bool 
     return logp, hidden
 
 
-def forward(theta, spins, m: Model, mode: str = "seq", keep_hidden: bool = False, bf16: bool = False):
+def forward(theta, spins, m: Model, mode: str = "seq", keep_hidden: bool = False):
     """Per-site log p in lattice row-major order, [B, N], and optionally hidden states.
 
     ``spins`` is an int array [B, N] with values in {0, 1}, row-major (site
     y * lx + x).  Returns ``(logp, hidden)``; ``hidden[l]`` is h^(l) at every
     site, [B, N, d], when ``keep_hidden`` is set, else ``None``.
-
-    ``bf16`` evaluates the reduced-precision reading of the model: the operands
-    of the dense projections (weight matrices acting on d-dimensional
-    activations, and those activations: x^(l>=1), h_V and h) are rounded to
-    bfloat16 (nearest, ties to even), the residual s = h^(l-1) is added in its
-    bfloat16 rounding (the row's h is kept once, in bfloat16), and everything
-    else is exact.  The chain
-    has no such projection, so the flag does not change it.
     """
     spins = np.asarray(spins)
     if spins.ndim != 2 or spins.shape[1] != m.n_sites:
@@ -331,12 +300,12 @@ def forward(theta, spins, m: Model, mode: str = "seq", keep_hidden: bool = False
     P = unpack(theta, m)
     if m.geometry == "chain":
         return _forward_chain(P, spins, m, mode, keep_hidden)
-    return _forward_snake(P, spins, m, mode, keep_hidden, bf16)
+    return _forward_snake(P, spins, m, mode, keep_hidden)
 
 
-def logpsi(theta, spins, m: Model, mode: str = "seq", bf16: bool = False) -> np.ndarray:
+def logpsi(theta, spins, m: Model, mode: str = "seq") -> np.ndarray:
     """log psi(sigma) = (1/2) sum_t log p_t, float64 [B]."""
-    logp, _ = forward(theta, spins, m, mode, bf16=bf16)
+    logp, _ = forward(theta, spins, m, mode)
     return 0.5 * logp.sum(axis=1)
 
 
