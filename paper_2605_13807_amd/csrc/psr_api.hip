@@ -107,7 +107,7 @@ void param_offsets(const Geom& g, int64_t* off, int32_t* n) {
 Prepared prepared_layout(const Geom& g) {
     Prepared pl;
     const int64_t d = g.d;
-    const int64_t mat = d * d * (g.prec == kBF16 ? 2 : 4);
+    const int64_t mat = d * d * 4;   // FP32 values, or BF16 high and low parts
     int64_t fb = 0;
     // absent matrices keep offset 0 (never read) so that pointer arithmetic stays in range
     for (int l = 0; l < 8; ++l)
@@ -164,7 +164,7 @@ struct Carver {
 // Per-sequence device scratch of the forward kernel: the row frontier h^(l)
 // of every layer (the next row's h_V), in the projections' operand type.
 static int64_t frontier_seq_bytes(const Geom& g) {
-    return (int64_t)g.nl * g.lx * g.d * (g.prec == kBF16 ? 2 : 4);
+    return (int64_t)g.nl * g.lx * g.d * 4;   // FP32 values, or BF16 high and low parts
 }
 
 // sequences per forward launch for psr_logpsi (bounds the frontier workspace to ~256 MB)

@@ -15,11 +15,22 @@
 //      the wave's tiles, then (if a row straddles waves) across waves through LDS.
 //      A row start has a = 0, which is how h_H = 0 outside the lattice enters
 //      and how packed sequences stay independent (segmented scan);
-//   3. h is stored as the row frontier (global workspace; read back as the
-//      MFMA operand h_V by the next row) and x = GELU(C h + D u + s) is formed
-//      on MFMA, with the residual rows s kept in LDS;
+//   3. h is stored as the row frontier (LDS when it fits, else a global
+//      workspace; read back as the MFMA operand h_V by the next row) and
+//      x = GELU(C h + D u + s) is formed on MFMA;
 //   4. after the last layer, the head gives log p of the site's own spin,
 //      accumulated per column with compensated (Neumaier) summation.
+//
+// Precision.  FP32: v_mfma_f32_16x16x4_f32.  BF16: every operand v of a dense
+// projection (weights and activations alike) is carried as two bfloat16 parts,
+// hi = bf16(v) and lo = bf16(v - hi), so that hi + lo holds v to about 16
+// significant bits, and a product W x is formed on v_mfma_f32_16x16x32_bf16 as
+// W_hi x_hi + W_lo x_hi + W_hi x_lo with FP32 accumulation (the dropped
+// W_lo x_lo term is ~2^-16 of the product).  A single bfloat16 rounding of the
+// operands perturbs this randomly initialised recurrence too much for the
+// local energy (per-configuration ratio errors of 0.1-1 at 20x20 and above);
+// the split keeps it at FP32-like accuracy for a third of the BF16 matrix rate,
+// still five times the FP32 matrix rate.
 #include "psr_internal.h"
 #include "gelu_fit.h"
 
@@ -32,14 +43,24 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int P> struct MF;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 template <> struct MF<kBF16> {
-    typedef u32x4 Frag;            // 8 bfloat16 values as 4 dwords (two per dword)
+    typedef u32x8 Frag;            // dwords 0-3: 8 bfloat16 high parts; dwords 4-7: their low parts
     static constexpr int K = 32;
-    static constexpr int ELT = 2;
-    __device__ static inline f32x4 mma(bf16x8 a, Frag b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    static constexpr int ELT = 4;  // bytes per value (hi and lo) in the row frontier
+    // c + a b with a = a_hi + a_lo, b = b_hi + b_lo:  a_hi b_hi + a_lo b_hi + a_hi b_lo
+    // (The halves are taken by shufflevector: hipcc's __builtin_bit_cast of a `.hi`
+    // swizzle reads the vector's first half.)
+    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, a, 0, 1, 2, 3));
+        const bf16x8 al = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, a, 4, 5, 6, 7));
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b, b, 0, 1, 2, 3));
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b, b, 4, 5, 6, 7));
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
     }
 };
 template <> struct MF<kFP32> {
@@ -60,6 +81,11 @@ __device__ __host__ inline int unit_pos(int u, int d) {
     return ((u >> 2) & 3) * (d >> 2) + 4 * (u >> 4) + (u & 3);
 }
 
+// bfloat16 high part of v (round to nearest even) and the float it stands for
+__device__ inline __bf16 bf16_hi(float v) { return (__bf16)v; }
+
+// BF16 weight fragments, split: for output tile mt and K block kb of 32, the
+// 64 lanes' 8 high parts (1 KB), then the 64 lanes' 8 low parts (1 KB).
 __global__ void prep_frag_bf16(const float* __restrict__ theta, MatSrc src, int d, __bf16* __restrict__ out) {
     const int64_t n = (int64_t)d * d;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,7 +97,12 @@ __global__ void prep_frag_bf16(const float* __restrict__ theta, MatSrc src, int 
     const int kb = (int)(f % nkb), mt = (int)(f / nkb);
     const int r = 16 * mt + (lane & 15), g = lane >> 4;
     const int k = slot_unit(8 * kb + j, g);
-    out[e] = (__bf16)theta[src.base + (int64_t)r * src.ld + src.coff + k];
+    const float v = theta[src.base + (int64_t)r * src.ld + src.coff + k];
+    const __bf16 hi = bf16_hi(v);
+    const __bf16 lo = (__bf16)(v - (float)hi);
+    const int64_t o = ((f * 2) * 64 + lane) * 8 + j;
+    out[o] = hi;
+    out[o + 512] = lo;
 }
 
 __global__ void prep_frag_f32(const float* __restrict__ theta, MatSrc src, int d, float* __restrict__ out) {
@@ -258,17 +289,13 @@ __device__ inline float carry_apply(float b, float a, float B) {
 
 // GELU(x) = x Phi(x) = max(x, 0) - |x| p(x) with the Gaussian tail
 // p(x) = erfc(|x|/sqrt 2)/2 ~ t Ph(t) 2^(-C x^2), t = 1/(1 + S|x|)
-// (coefficients fitted by gen_gelu_fit.py).  DEG 5 is accurate to float32;
-// DEG 4 (abs. error ~1e-7) serves outputs that are rounded to bfloat16 next.
-template <int DEG = 5>
+// (degree-5 coefficients fitted by gen_gelu_fit.py, accurate to float32).
 __device__ inline float gelu_tail(float x) {
-    const float* P = (DEG == 5) ? kGeluP : kGeluP4;
-    const float S = (DEG == 5) ? kGeluS : kGeluS4;
     const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(ax, S, 1.0f));
-    float q = P[0];
+    const float t = __builtin_amdgcn_rcpf(fmaf(ax, kGeluS, 1.0f));
+    float q = kGeluP[0];
 #pragma unroll
-    for (int k = 1; k <= DEG; ++k) q = fmaf(q, t, P[k]);
+    for (int k = 1; k <= 5; ++k) q = fmaf(q, t, kGeluP[k]);
     const float p = (t * q) * __builtin_amdgcn_exp2f((x * x) * -kGeluC);
     // max(x, 0) on the bit pattern: a negative float is a negative int32
     const float xp = __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
@@ -281,34 +308,34 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-// A operand (weights) of one 16-row output tile, in 16-byte pieces per lane:
-// BF16 one K-block of 32 per piece, FP32 four K-steps of 4 per piece.
+// A operand (weights) of one 16-row output tile, per lane: BF16 one K block of
+// 32 per piece (8 high and 8 low parts), FP32 four K steps of 4 per piece.
 template <int P, int D>
 struct AOp {
     static constexpr int N = (P == kBF16) ? D / 32 : D / 16;
-    typedef typename std::conditional<P == kBF16, bf16x8, f32x4>::type T;
+    typedef typename std::conditional<P == kBF16, u32x8, f32x4>::type T;
 };
 
+// The weight fragments come through buffer loads: the matrix base and the tile
+// offset stay scalar and the lane offset is one constant vector register, which
+// frees the registers that per-tile 64-bit addresses would hold (such kernels
+// spilled without it); the descriptor bounds the matrix (an out-of-range lane
+// would read zeros).  A tile is D * 64 bytes in both precisions.
 template <int P, int D, class W>
 __device__ inline void load_a(W& w, const uint8_t* __restrict__ mat, int mt, int lane) {
-    typedef typename AOp<P, D>::T T;
-    constexpr int TILE = AOp<P, D>::N * 64 * (int)sizeof(T);   // bytes of one output tile's fragments
-    // Large tiles (FP32, or d = 256) use buffer loads: the matrix base and the tile
-    // offset stay scalar and the lane offset is one constant vector register, which
-    // frees the registers that per-tile 64-bit addresses would hold (those kernels
-    // spilled without it); the descriptor bounds the matrix (an out-of-range lane
-    // would read zeros).  BF16 at d <= 128 measured faster with plain global loads.
-    constexpr bool BUF = (P == kFP32) || D >= 256;
-    if constexpr (BUF) {
-        const __amdgpu_buffer_rsrc_t r =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(mat), 0, TILE * (D / 16), 0x00020000);
+    constexpr int TILE = D * 64;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(mat), 0, TILE * (D / 16), 0x00020000);
 #pragma unroll
-        for (int k = 0; k < AOp<P, D>::N; ++k)
-            w[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 1024, mt * TILE, 0));
-    } else {
-        const T* A = reinterpret_cast<const T*>(mat + (size_t)mt * TILE) + lane;
-#pragma unroll
-        for (int k = 0; k < AOp<P, D>::N; ++k) w[k] = A[k * 64];
+    for (int k = 0; k < AOp<P, D>::N; ++k) {
+        if constexpr (P == kBF16) {
+            const u32x4 hi = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 2048, mt * TILE, 0));
+            const u32x4 lo =
+                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 2048 + 1024, mt * TILE, 0));
+            w[k] = __builtin_shufflevector(hi, lo, 0, 1, 2, 3, 4, 5, 6, 7);
+        } else {
+            w[k] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 1024, mt * TILE, 0));
+        }
     }
 }
 
@@ -400,14 +427,22 @@ __device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC],
     }
 }
 
-// slots s, s+1 (s even) of a lane's operand array; BF16 packs the pair into one dword
+// slots s, s+1 (s even) of a lane's operand array.  BF16 packs the pair's high
+// parts into one dword of the fragment's first half and their low parts
+// (v - hi, rounded again) into the same dword of the second half.
 template <int P, int D>
 __device__ inline void set_pair(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, float x0, float x1) {
     if constexpr (P == kBF16) {
         bf16x2 v;
-        v[0] = (__bf16)x0;
-        v[1] = (__bf16)x1;
-        f[s >> 3][(s & 7) >> 1] = __builtin_bit_cast(uint32_t, v);
+        v[0] = bf16_hi(x0);
+        v[1] = bf16_hi(x1);
+        const uint32_t hu = __builtin_bit_cast(uint32_t, v);
+        bf16x2 w;
+        w[0] = (__bf16)(x0 - __builtin_bit_cast(float, hu << 16));
+        w[1] = (__bf16)(x1 - __builtin_bit_cast(float, hu & 0xFFFF0000u));
+        const int q = (s & 7) >> 1;
+        f[s >> 3][q] = hu;
+        f[s >> 3][4 + q] = __builtin_bit_cast(uint32_t, w);
     } else {
         f[s] = x0;
         f[s + 1] = x1;
@@ -420,26 +455,31 @@ __device__ inline void set_pair(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, 
 template <int P, int D>
 __device__ inline void pin_tile(typename MF<P>::Frag (&f)[D / MF<P>::K], int mt) {
     if constexpr (P == kBF16) {
-        asm volatile("" ::"v"(f[mt >> 1][2 * (mt & 1)]), "v"(f[mt >> 1][2 * (mt & 1) + 1]));
+        const int q = 2 * (mt & 1);
+        asm volatile("" ::"v"(f[mt >> 1][q]), "v"(f[mt >> 1][q + 1]), "v"(f[mt >> 1][4 + q]), "v"(f[mt >> 1][5 + q]));
     } else {
         asm volatile("" ::"v"(f[4 * mt]), "v"(f[4 * mt + 1]), "v"(f[4 * mt + 2]), "v"(f[4 * mt + 3]));
     }
 }
 __device__ inline void pin1(float& x) { asm volatile("" : "+v"(x)); }
 
-// Row frontier (h of the previous row, the operand type of the projections):
+// Row frontier (h of the previous row, in the projections' operand form):
 // per sequence-local index qi, layer l, physical column i, lane group g, the
-// lane's d/4 slots are contiguous, so a lane moves whole 16-byte fragments.
+// lane's d/4 slots are contiguous (BF16: per fragment, the 16 bytes of high
+// parts, then the 16 bytes of low parts), so a lane moves whole 16-byte pieces.
 template <int ELT, int D>
 __device__ inline uint8_t* col_ptr(void* base, int64_t qi, int l, int nslot, int lx, int i, int g) {
     return reinterpret_cast<uint8_t*>(base) + ((((size_t)qi * nslot + l) * lx + i) * D + (size_t)g * (D / 4)) * ELT;
 }
 
-// 16-byte pieces of a lane's operand array (BF16: one fragment; FP32: four slots)
+// 16-byte pieces of a lane's operand array (BF16: half a fragment, high parts
+// first; FP32: four slots)
 template <int P, int D>
 __device__ inline void frag_set16(typename MF<P>::Frag (&f)[D / MF<P>::K], int k, f32x4 v) {
     if constexpr (P == kBF16) {
-        f[k] = __builtin_bit_cast(u32x4, v);
+        const u32x4 u = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f[k >> 1][4 * (k & 1) + e] = u[e];
     } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) f[4 * k + e] = v[e];
@@ -447,10 +487,12 @@ __device__ inline void frag_set16(typename MF<P>::Frag (&f)[D / MF<P>::K], int k
 }
 template <int P, int D>
 __device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K], int k) {
-    if constexpr (P == kBF16)
-        return __builtin_bit_cast(f32x4, f[k]);
-    else
+    if constexpr (P == kBF16) {
+        const int o = 4 * (k & 1);
+        return __builtin_bit_cast(f32x4, u32x4{f[k >> 1][o], f[k >> 1][o + 1], f[k >> 1][o + 2], f[k >> 1][o + 3]});
+    } else {
         return f32x4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
+    }
 }
 
 // 16 bytes at a uniform float base plus a per-lane byte offset that fits 32 bits
@@ -613,7 +655,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 
         // GEMM1 operand slots (fragments and seeds of two tiles), at row scope so that a
         // layer can load the next layer's first two tiles during its last output tiles
-        constexpr bool PFK = 3 * NA <= 12;   // layers >= 1 run the pipelined path
+        // layers >= 1 run the pipelined path when two slots of a tile's fragments are few registers
+        constexpr bool PFK = 3 * NA * (int)sizeof(AT) <= 12 * 16;
         AT w1r[2][3][NA];
         f32x4 s1zr[2][NTC], s1hr[2][NTC];
         bool pre1 = false;   // the next layer's tiles 0 and 1 are in w1r / s1zr / s1hr
@@ -687,7 +730,6 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             };
             // GEMM2 operands of tile mt: fragments, the seed (layer 0: table row of D u;
             // else the residual row, zero for layer 1) and the head rows (last layer)
-            uint2 rhold[NTC];   // second half of the last 16-byte residual read
             auto seeds2 = [&](int mt, f32x4 (&so)[NTC]) {
                 if constexpr (!CHAIN) {
                     if constexpr (FIRST) {
@@ -699,18 +741,17 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
                             if constexpr (P == kBF16) {
-                                // 16-byte reads (conflict-free on the padded rows) cover two tiles;
-                                // tiles are fetched in order, so an odd tile uses the held half
-                                uint2 v;
-                                if ((mt & 1) == 0) {
-                                    const uint4 q = *reinterpret_cast<const uint4*>(rsrc[c] + 8 * mt);
-                                    v = uint2{q.x, q.y};
-                                    rhold[c] = uint2{q.z, q.w};
-                                } else {
-                                    v = rhold[c];
-                                }
-                                so[c] = f32x4{__builtin_bit_cast(float, v.x << 16), __builtin_bit_cast(float, v.x & 0xFFFF0000u),
-                                              __builtin_bit_cast(float, v.y << 16), __builtin_bit_cast(float, v.y & 0xFFFF0000u)};
+                                // slots 4mt..4mt+3: two dwords of high parts and the two
+                                // dwords of their low parts, 16 bytes further on
+                                const uint8_t* q = rsrc[c] + (mt >> 1) * 32 + (mt & 1) * 8;
+                                const uint2 vh = *reinterpret_cast<const uint2*>(q);
+                                const uint2 vl = *reinterpret_cast<const uint2*>(q + 16);
+                                so[c] = f32x4{__builtin_bit_cast(float, vh.x << 16) + __builtin_bit_cast(float, vl.x << 16),
+                                              __builtin_bit_cast(float, vh.x & 0xFFFF0000u) +
+                                                  __builtin_bit_cast(float, vl.x & 0xFFFF0000u),
+                                              __builtin_bit_cast(float, vh.y << 16) + __builtin_bit_cast(float, vl.y << 16),
+                                              __builtin_bit_cast(float, vh.y & 0xFFFF0000u) +
+                                                  __builtin_bit_cast(float, vl.y & 0xFFFF0000u)};
                                 if constexpr (!LDSF) so[c] = so[c] * rs;   // layer 1 has no residual
                             } else {
                                 so[c] = *reinterpret_cast<const f32x4*>(rsrc[c] + 16 * mt) * rs;
@@ -877,10 +918,8 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                     if constexpr (!LAST) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
-                            // the next layer's input is rounded to bfloat16 on the BF16 path
-                            constexpr int GD = (P == kBF16) ? 4 : 5;
-                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail<GD>(ao[sl][c][0]), gelu_tail<GD>(ao[sl][c][1]));
-                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail<GD>(ao[sl][c][2]), gelu_tail<GD>(ao[sl][c][3]));
+                            set_pair<P, D>(xn[c], 4 * mt, gelu_tail(ao[sl][c][0]), gelu_tail(ao[sl][c][1]));
+                            set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[sl][c][2]), gelu_tail(ao[sl][c][3]));
                             pin_tile<P, D>(xn[c], mt);
                         }
                     } else {
@@ -1009,11 +1048,12 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
 // ---------------------------------------------------------------------------
 
 // Tiles per wave, chosen so that the four register-resident operand sets
-// (layer input, h_V, h, next input) fit without spills.
-static int ntc_for(int prec, int d) {
-    if (prec == kBF16) return d <= 64 ? 4 : (d == 128 ? 2 : 1);
-    if (d <= 32) return 4;
-    return d <= 128 ? 2 : 1;
+// (layer input, h_V, h, next input) fit.  A split BF16 operand takes the
+// registers of an FP32 one, so both precisions use the same shapes.  The launch
+// (template argument) and the host-side sizing (fwd_shape) both take it from here.
+static constexpr int ntc_for(int prec, int d) {
+    (void)prec;
+    return d <= 32 ? 4 : (d <= 128 ? 2 : 1);
 }
 
 FwdShape fwd_shape(const Geom& g) {
@@ -1028,9 +1068,10 @@ FwdShape fwd_shape(const Geom& g) {
         const int c0 = k * g.lx, c1 = (k + 1) * g.lx - 1;
         if (c0 / per_wave != c1 / per_wave) s.cross_wave = 1;
     }
-    const int64_t pitch = (int64_t)g.d * 2 + 16;
+    // BF16 frontier rows: d values of 4 bytes (high and low parts) plus 16 bytes of padding
+    const int64_t pitch = (int64_t)g.d * 4 + 16;
     s.lds_frontier = (!g.chain && g.prec == kBF16 &&
-                      (int64_t)g.d * 2 + (int64_t)s.seqs * g.nl * g.lx * pitch <= kLdsFrontier) ? 1 : 0;
+                      (int64_t)g.d * 4 + (int64_t)s.seqs * g.nl * g.lx * pitch <= kLdsFrontier) ? 1 : 0;
     return s;
 }
 
@@ -1066,19 +1107,20 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
 
 int launch_forward(const FwdArgs& a, hipStream_t st) {
     const int d = a.g.d;
+    if (a.sh.ntc != ntc_for(a.g.prec, d)) return (int)hipErrorInvalidValue;   // shape from another model
     if (a.g.prec == kBF16) {
         switch (d) {
-            case 32: return launch_t<kBF16, 32, 4>(a, st);
-            case 64: return launch_t<kBF16, 64, 4>(a, st);
-            case 128: return launch_t<kBF16, 128, 2>(a, st);
-            case 256: return launch_t<kBF16, 256, 1>(a, st);
+            case 32: return launch_t<kBF16, 32, ntc_for(kBF16, 32)>(a, st);
+            case 64: return launch_t<kBF16, 64, ntc_for(kBF16, 64)>(a, st);
+            case 128: return launch_t<kBF16, 128, ntc_for(kBF16, 128)>(a, st);
+            case 256: return launch_t<kBF16, 256, ntc_for(kBF16, 256)>(a, st);
         }
     } else {
         switch (d) {
-            case 32: return launch_t<kFP32, 32, 4>(a, st);
-            case 64: return launch_t<kFP32, 64, 2>(a, st);
-            case 128: return launch_t<kFP32, 128, 2>(a, st);
-            case 256: return launch_t<kFP32, 256, 1>(a, st);
+            case 32: return launch_t<kFP32, 32, ntc_for(kFP32, 32)>(a, st);
+            case 64: return launch_t<kFP32, 64, ntc_for(kFP32, 64)>(a, st);
+            case 128: return launch_t<kFP32, 128, ntc_for(kFP32, 128)>(a, st);
+            case 256: return launch_t<kFP32, 256, ntc_for(kFP32, 256)>(a, st);
         }
     }
     return (int)hipErrorInvalidValue;

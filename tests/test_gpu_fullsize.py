@@ -1,11 +1,28 @@
-"""GPU parity at the full 32x32 workload, in the launch configuration that bench.py times.
+"""GPU parity at the full workload shapes, in the launch configuration that bench.py times.
 
-The 32x32 open Heisenberg model (3 layers, d = 128) with the benchmark's seeds,
-4096 Neel-like samples and E_loc streamed in 32768-sequence chunks.  The oracle
-cannot evaluate the whole workload, so it checks sampled outputs one by one;
-everything else is checked through properties that hold at any size.
-Tolerances are those of test_gpu_parity.py.
+The oracle cannot evaluate a whole full-size step, so it checks sampled outputs;
+everything else is checked through properties that hold at any size.  The
+float64 local energies of the samples checked here were written by
+``tests/golden/gen_fullsize_eloc.py`` (which calls only the oracle and the
+seeded generators); the rest is computed by the oracle at test time.
+
+  32x32, 3 layers, d = 128 (4096 Neel-like samples, E_loc streamed in chunks of
+      32768 sequences): E_loc and log psi of the first 64 samples against the
+      stored oracle values (BF16 and FP32), the FP64 statistics of the returned
+      E_loc, and one per-sample gradient row against the oracle's autograd.
+  52x52, 4 layers, d = 256 (256 samples): E_loc of the first 2 samples (about
+      5300 connected configurations each) and log psi of the first 64 against
+      the stored oracle values, and the gradient rows of 2 samples against the
+      oracle's autograd.
+  20x20, 3 layers, d = 128 (checkpoint chunks of 3 rows, the 60 sites that are
+      the whole rows within 64 sites): O rows of 2 samples against central
+      finite differences of the oracle on 64 parameters (at least 2 per tensor).
+
+Bars are those of test_gpu_parity.py.
 """
+
+import math
+import os
 
 import numpy as np
 import pytest
@@ -13,14 +30,12 @@ import torch
 
 import psr_inputs as I
 from oracle import grad as OG
-from oracle import hamiltonian as OH
 from oracle import model as OM
 
 pytestmark = pytest.mark.gpu
 
-L, NL, D, SEED = 32, 3, 128, 3     # the heisenberg32x32 workload: lattice side, layers, width, seed index
-B_FULL, CHUNK = 4096, 32768
-SAMPLED = (0, 2731)                # samples checked against the oracle
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CHUNK = 32768
 
 
 @pytest.fixture(scope="module")
@@ -31,106 +46,132 @@ def P():
     return P
 
 
-def _setup(P, prec, B):
-    m = P.Model(P.SNAKE_2D, L, L, NL, D, prec)
-    om = OM.Model("snake2d", L, L, NL, D)
+def _golden(name):
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, f"{name}_oracle_eloc.txt")) if not ln.startswith("#")]
+    idx = np.array([int(r[0]) for r in rows])
+    n_conn = np.array([int(r[1]) for r in rows])
+    lp = np.array([float(r[2]) for r in rows])
+    e = np.array([float(r[3]) for r in rows])
+    assert np.array_equal(idx, np.arange(len(rows)))
+    return n_conn, lp, e
+
+
+def _setup(P, prec, L, nl, d, k, B, ckpt_rows=0):
+    m = P.Model(P.SNAKE_2D, L, L, nl, d, prec, ckpt_rows)
+    om = OM.Model("snake2d", L, L, nl, d)
     assert P.param_count(m) == OM.n_params(om)
-    th = I.params(OM.n_params(om), D, 1000 + SEED)
-    s = I.spins_neel_like(B, L, L, 2000 + SEED)
+    th = I.params(OM.n_params(om), d, 1000 + k)
+    s = I.spins_neel_like(B, L, L, 2000 + k)
     return m, om, th, s
 
 
-def _logpsi64(P, m, th_d, seqs):
-    """log psi summed in float64 from the per-site log p the kernel sums itself."""
-    _, lps = P.logpsi(m, th_d, seqs, site_logp=True)
-    return 0.5 * lps.double().sum(dim=1).cpu().numpy()
+def _check_eloc(P, prec, e, lp, n_conn_dev, ref_n, ref_lp, ref_e, N, label):
+    n_e = int(np.sum(np.isfinite(ref_e)))
+    assert np.array_equal(n_conn_dev[:n_e], ref_n[:n_e])
+    rel = np.abs(e[:n_e] - ref_e[:n_e]) / np.maximum(np.abs(ref_e[:n_e]), 1.0)
+    dlp = np.abs(lp[: len(ref_lp)] - ref_lp)
+    lp_tol = 2e-3 * math.sqrt(N) if prec == 1 else 1e-5 + 1e-6 * np.abs(ref_lp).max()
+    mean_rel = abs(e[:n_e].mean() - ref_e[:n_e].mean()) / max(1.0, abs(ref_e[:n_e].mean()))
+    print(f"  {label}: {n_e} samples, max rel E_loc err {rel.max():.3e}, mean {mean_rel:.3e}; "
+          f"{len(ref_lp)} samples, max |d log psi| {dlp.max():.3e} (tol {lp_tol:.2e})", flush=True)
+    assert rel.max() <= (1e-3 if prec == 1 else 1e-4)
+    assert mean_rel <= (1e-4 if prec == 1 else 1e-5)
+    assert dlp.max() <= lp_tol
+    return rel.max(), dlp.max()
 
 
-def _eloc_from_logpsi(P, m, th_d, H, s_one):
-    """E_loc of one sample from the library's own log psi of its connected set (float64 combine)."""
-    c = P.connected(H, s_one, configs=True)
-    n = int(c["n_conn"][0].item())
-    conf = c["conn"][0, :n].contiguous()
-    lp0 = _logpsi64(P, m, th_d, s_one)[0]
-    lpc = _logpsi64(P, m, th_d, conf)
-    mel = c["mel"][0, :n].double().cpu().numpy()
-    return float(c["diag"][0].item()) + float(np.sum(mel * np.exp(lpc - lp0))), conf
-
-
-def test_fullsize_local_energy_bf16(P):
-    print(f"full-size E_loc: {L}x{L} nl={NL} d={D} BF16 B={B_FULL} chunk={CHUNK}", flush=True)
-    m, om, th, s = _setup(P, P.BF16, B_FULL)
-    th_d = torch.from_numpy(th).cuda()
-    s_d = torch.from_numpy(s).cuda()
+@pytest.mark.parametrize("prec,B", [(1, 4096), (0, 64)])
+def test_fullsize32_local_energy(P, prec, B):
+    L, nl, d, k = 32, 3, 128, 3
+    print(f"full-size E_loc: {L}x{L} nl={nl} d={d} prec={prec} B={B} chunk={CHUNK}", flush=True)
+    ref_n, ref_lp, ref_e = _golden("heisenberg32x32")
+    m, om, th, s = _setup(P, prec, L, nl, d, k, B)
+    th_d, s_d = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
     H = P.Hamiltonian(P.HEISENBERG, L, L)
     e, st, lp = P.local_energy(m, th_d, H, s_d, chunk_seqs=CHUNK)
-    e = e.cpu().numpy()
-    st = st.cpu().numpy()
+    n_conn = P.connected(H, s_d[:64])["n_conn"].cpu().numpy()
+    e, st, lp = e.cpu().numpy(), st.cpu().numpy(), lp.cpu().numpy().astype(np.float64)
     assert np.all(np.isfinite(e))
     # FP64 statistics of exactly the returned E_loc
     assert abs(st[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
     assert abs(st[1] - e.var()) <= 1e-10 * max(1.0, abs(e.var()))
-    # the samples' log psi: the same kernel in a different launch composition
+    _check_eloc(P, prec, e, lp, n_conn, ref_n, ref_lp, ref_e, L * L, "vs float64 oracle")
+    # the samples' log psi from psr_local_energy equals psr_logpsi's (other launch composition)
     lp_alone = P.logpsi(m, th_d, s_d).cpu().numpy()
-    lp = lp.cpu().numpy()
     assert np.abs(lp - lp_alone).max() <= 1e-6 * max(1.0, np.abs(lp).max())
-    rng = np.random.default_rng(5)
-    for k in SAMPLED:
-        # E_loc of this sample rebuilt from its connected set, evaluated in a small launch
-        e_k, conf = _eloc_from_logpsi(P, m, th_d, H, s_d[k:k + 1])
-        print(f"  sample {k}: E_loc {e[k]:.9f} streamed vs {e_k:.9f} rebuilt, {conf.shape[0]} connected")
-        assert abs(e[k] - e_k) <= 1e-5 * max(1.0, abs(e_k))
-        # log psi of the sample and of 15 sampled connected configurations against the BF16 reading
-        pick = torch.from_numpy(rng.choice(conf.shape[0], size=15, replace=False)).to(conf.device)
-        seqs = np.concatenate([s[k:k + 1], conf[pick].cpu().numpy()], axis=0)
-        got = P.logpsi(m, th_d, torch.from_numpy(seqs).cuda()).double().cpu().numpy()
-        reading = OM.logpsi(th, seqs, om, bf16=True)
-        exact = OM.logpsi(th, seqs, om)
-        err = np.abs(got - reading).max()
-        dev_r = np.abs(reading - exact).max()
-        print(f"    log psi vs BF16 reading {err:.3e}; reading vs exact {dev_r:.3e}")
-        assert err <= 1e-4 + 0.5 * dev_r
 
 
-def test_fullsize_local_energy_fp32_sampled(P):
-    B = 64      # about 1.8k connected each: three full 32768-sequence launches and a partial one
-    print(f"full-size E_loc: {L}x{L} nl={NL} d={D} FP32 B={B} chunk={CHUNK}", flush=True)
-    m, om, th, s = _setup(P, P.FP32, B)
-    th_d = torch.from_numpy(th).cuda()
-    H = P.Hamiltonian(P.HEISENBERG, L, L)
-    e, st, lp = P.local_energy(m, th_d, H, torch.from_numpy(s).cuda(), chunk_seqs=CHUNK)
-    e = e.cpu().numpy()
-    k = SAMPLED[0]
-    oh = OH.Hamiltonian("heisenberg", L, L, J=1.0)
-    ref = OH.local_energy(lambda c: OM.logpsi(th, c, om), oh, s[k:k + 1])[0]
-    rel = abs(e[k] - ref) / max(abs(ref), 1.0)
-    print(f"  sample {k}: E_loc {e[k]:.9f} vs oracle {ref:.9f} (rel {rel:.2e})")
-    assert rel <= 1e-4
-    lp_ref = OM.logpsi(th, s[k:k + 1], om)[0]
-    assert abs(float(lp[k]) - lp_ref) <= 1e-5 + 1e-6 * abs(lp_ref)
-
-
-def test_fullsize_gradient_sampled(P):
-    print(f"full-size gradient: {L}x{L} nl={NL} d={D} BF16 model B={B_FULL}", flush=True)
-    m, om, th, s = _setup(P, P.BF16, B_FULL)
-    th_d = torch.from_numpy(th).cuda()
-    s_d = torch.from_numpy(s).cuda()
+def test_fullsize32_gradient_sampled(P):
+    L, nl, d, k, B = 32, 3, 128, 3, 4096
+    print(f"full-size gradient: {L}x{L} nl={nl} d={d} BF16 model B={B}", flush=True)
+    m, om, th, s = _setup(P, P.BF16, L, nl, d, k, B)
+    th_d, s_d = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
     rng = np.random.default_rng(11)
-    w = torch.from_numpy(rng.standard_normal(B_FULL) / B_FULL).cuda()
+    w = torch.from_numpy(rng.standard_normal(B) / B).cuda()
     O, lpb, g = P.logpsi_backward(m, th_d, s_d, w=w, want_O=True)
     assert torch.isfinite(O).all()
     # the estimator is the FP64 weighted sum of exactly the returned rows
     g_ref = torch.zeros(O.shape[1], dtype=torch.float64, device=O.device)
-    for i in range(0, B_FULL, 512):
+    for i in range(0, B, 512):
         g_ref += w[i:i + 512] @ O[i:i + 512].double()
     gerr = (g - g_ref).abs().max().item() / max(1e-30, g_ref.abs().max().item())
     print(f"  estimator vs FP64 sum of the rows: {gerr:.2e}")
     assert gerr <= 1e-10
-    k = SAMPLED[1]
-    lp_ref, O_ref = OG.per_sample_grad(th, s[k:k + 1], om)
-    Ok = O[k].double().cpu().numpy()
+    kk = 2731
+    lp_ref, O_ref = OG.per_sample_grad(th, s[kk:kk + 1], om)
+    Ok = O[kk].double().cpu().numpy()
     rel = np.linalg.norm(Ok - O_ref[0]) / np.linalg.norm(O_ref[0])
-    print(f"  sample {k}: rel grad err {rel:.2e}; log psi {float(lpb[k]):.6f} vs {lp_ref[0]:.6f}")
+    print(f"  sample {kk}: rel grad err {rel:.2e}; log psi {float(lpb[kk]):.6f} vs {lp_ref[0]:.6f}")
     assert rel <= 1e-4
-    # the backward runs in FP32: its log psi is the FP32 model's
-    assert abs(float(lpb[k]) - lp_ref[0]) <= 1e-5 + 1e-6 * abs(lp_ref[0])
+    assert abs(float(lpb[kk]) - lp_ref[0]) <= 1e-5 + 1e-6 * abs(lp_ref[0])
+
+
+@pytest.mark.parametrize("prec,B", [(1, 256), (0, 2)])
+def test_fullsize52_local_energy(P, prec, B):
+    L, nl, d, k = 52, 4, 256, 4
+    print(f"full-size E_loc: {L}x{L} nl={nl} d={d} prec={prec} B={B} chunk={CHUNK}", flush=True)
+    ref_n, ref_lp, ref_e = _golden("heisenberg52x52")
+    m, om, th, s = _setup(P, prec, L, nl, d, k, max(B, 64))
+    th_d, s_d = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
+    H = P.Hamiltonian(P.HEISENBERG, L, L)
+    e, st, lp = P.local_energy(m, th_d, H, s_d[:B], chunk_seqs=CHUNK)
+    e = e.cpu().numpy()
+    lp64 = P.logpsi(m, th_d, s_d[:64]).cpu().numpy().astype(np.float64)
+    n_conn = P.connected(H, s_d[:2])["n_conn"].cpu().numpy()
+    assert np.all(np.isfinite(e))
+    assert abs(st.cpu().numpy()[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
+    _check_eloc(P, prec, e, lp64, n_conn, ref_n, ref_lp, ref_e, L * L, "vs float64 oracle")
+
+
+def test_fullsize52_gradient_rows(P):
+    L, nl, d, k = 52, 4, 256, 4
+    print(f"full-size gradient: {L}x{L} nl={nl} d={d} 2 samples", flush=True)
+    m, om, th, s = _setup(P, P.BF16, L, nl, d, k, 2)
+    O, lpb, _ = P.logpsi_backward(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda())
+    lp_ref, O_ref = OG.per_sample_grad(th, s, om)
+    O = O.double().cpu().numpy()
+    rel = np.linalg.norm(O - O_ref, axis=1) / np.linalg.norm(O_ref, axis=1)
+    print(f"  per-sample rel grad err {rel}; log psi {lpb.cpu().numpy()} vs {lp_ref}")
+    assert rel.max() <= 1e-4
+
+
+def test_fullsize20_gradient_finite_differences(P):
+    L, nl, d, k = 20, 3, 128, 2
+    R = 64 // L      # checkpoint chunks of whole rows within 64 sites: 3 rows = 60 sites
+    print(f"20x20 gradient vs finite differences: nl={nl} d={d} ckpt_rows={R}", flush=True)
+    m, om, th, s = _setup(P, P.FP32, L, nl, d, k, 2, ckpt_rows=R)
+    O, _, _ = P.logpsi_backward(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda())
+    O = O.double().cpu().numpy()
+    offs = P.param_offsets(m)
+    rng = np.random.default_rng(20)
+    idx = []
+    for t in range(len(offs) - 1):
+        idx += list(rng.choice(np.arange(offs[t], offs[t + 1]), size=2, replace=False))
+    idx += list(rng.choice(np.arange(offs[-1]), size=max(0, 64 - len(idx)), replace=False))
+    idx = np.array(sorted(set(int(i) for i in idx)))
+    assert len(idx) >= 64
+    fd = np.stack([OG.finite_difference(th, s, om, int(i)) for i in idx], axis=1)   # [2, n]
+    got = O[:, idx]
+    rel = np.linalg.norm(got - fd, axis=1) / np.linalg.norm(fd, axis=1)
+    print(f"  {len(idx)} parameters: rel err per sample {rel}")
+    assert rel.max() <= 1e-4

@@ -1,21 +1,17 @@
 """GPU parity: the HIP library (through its C ABI) against the float64 oracle.
 
-Tolerances (derived from the arithmetic of each path):
+Both precisions are compared with the plain float64 oracle, at fixed bars:
   connected configurations, matrix elements, diagonal   bit-exact
-  FP32 path   max |d log psi| <= 1e-5 + 1e-6 |log psi|  (about 16 float32 ulps of log psi)
-  BF16 path   compared with the oracle's BF16 reading (projection operands
-              rounded to bfloat16, everything else exact).  The kernel rounds
-              float32 values, the reading float64 ones, so a value lying within
-              float32 error of a bfloat16 rounding boundary can round the other
-              way; each such flip is a full bfloat16 ulp and the random-weight
-              model amplifies it like any other rounding.  The check is
-              therefore relative to the reading's own distance from the exact
-              model:  max |kernel - reading| <= 1e-4 + 0.5 max |reading - exact|
-              for log psi (the kernel reproduces at least half of the BF16
-              deviation) and <= the reading's own deviation per site; the
-              deviation from the exact float64 model is printed.
-  E_loc       max_s |dE| / max(|E|, 1) <= 1e-4 (FP32); BF16 against the reading
-              <= 5e-3
+  log psi     FP32: max |d log psi| <= 1e-5 + 1e-6 |log psi| (about 16 float32
+              ulps of log psi), per site <= 1e-4.
+              BF16: max |d log psi| <= 2e-3 sqrt(N), per site <= 1e-3.  The BF16
+              path carries every projection operand as a bfloat16 pair
+              (hi + lo, ~16 significant bits) and forms each product from three
+              BF16 matrix products, so its error is a few hundred float32 ulps
+              amplified by the recurrence; 2e-3 sqrt(N) is the gate of a random
+              walk of per-site errors of 2e-3.
+  E_loc       max_s |dE| / max(|E|, 1) <= 1e-4 (FP32), <= 1e-3 (BF16); the mean
+              to 1e-5 (FP32) and 1e-4 (BF16) relative.
   gradients   per sample ||dO|| / ||O|| <= 1e-4 (the backward runs in FP32)
 """
 
@@ -60,9 +56,15 @@ def _case(P, geom, lx, ly, nl, d, prec, B, seed, ckpt_rows=0, spins="bern"):
     return m, om, th, s
 
 
-def _tol(prec, ref):
-    scale = float(np.abs(ref).max())
-    return 1e-5 + 1e-6 * scale
+def _tol(prec, ref, n_sites):
+    """Bar on max |d log psi| against the float64 oracle (see the module docstring)."""
+    if prec == 1:
+        return 2e-3 * math.sqrt(n_sites)
+    return 1e-5 + 1e-6 * float(np.abs(ref).max())
+
+
+def _site_tol(prec):
+    return 1e-3 if prec == 1 else 1e-4
 
 
 # ----------------------------------------------------------------------------
@@ -155,27 +157,18 @@ LOGPSI_CASES = [
 def test_logpsi_parity(P, geom, lx, ly, nl, d, prec, B):
     print(f"logpsi case geom={geom} {lx}x{ly} nl={nl} d={d} prec={prec} B={B}", flush=True)
     m, om, th, s = _case(P, geom, lx, ly, nl, d, prec, B, seed=lx + 3 * ly + d)
-    ref_site, _ = OM.forward(th, s, om, bf16=(prec == 1))
+    ref_site, _ = OM.forward(th, s, om)
     ref = 0.5 * ref_site.sum(axis=1)
     got, site = P.logpsi(m, torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda(), site_logp=True)
     got = got.cpu().numpy().astype(np.float64)
     site = site.cpu().numpy().astype(np.float64)
     err = np.abs(got - ref).max()
     serr = np.abs(site - ref_site).max()
-    if prec == 0:
-        print(f"  max|dlogpsi| = {err:.3e} (tol {_tol(prec, ref):.3e}); max site err {serr:.3e}")
-        assert err <= _tol(prec, ref)
-        assert serr <= 1e-4
-    else:
-        exact_site, _ = OM.forward(th, s, om)
-        exact = 0.5 * exact_site.sum(axis=1)
-        dev_r = np.abs(ref - exact).max()
-        dev_rs = np.abs(ref_site - exact_site).max()
-        print(f"  vs BF16 reading: max|dlogpsi| = {err:.3e}, site {serr:.3e}; "
-              f"reading vs exact: {dev_r:.3e}, site {dev_rs:.3e}; "
-              f"kernel vs exact float64: {np.abs(got - exact).max():.3e} (|log psi| ~ {np.abs(exact).max():.1f})")
-        assert err <= 1e-4 + 0.5 * dev_r
-        assert serr <= 1e-4 + dev_rs
+    tol = _tol(prec, ref, lx * ly)
+    print(f"  max|dlogpsi| = {err:.3e} (tol {tol:.3e}, |log psi| ~ {np.abs(ref).max():.1f}); "
+          f"max site err {serr:.3e} (tol {_site_tol(prec):.0e})")
+    assert err <= tol
+    assert serr <= _site_tol(prec)
 
 
 def test_logpsi_determinism_and_batch_invariance(P):
@@ -219,6 +212,9 @@ ELOC_CASES = [
     (1, 10, 10, 2, 64, 1, 1, 48, "zero", 32768),
     (1, 4, 3, 3, 32, 0, 1, 20, "bern", 7),         # tiny chunks, ragged
     (1, 6, 4, 2, 32, 0, 0, 16, "bern", 32768),     # 2D TFIM
+    (1, 6, 4, 2, 32, 1, 0, 16, "bern", 32768),
+    (1, 20, 20, 3, 128, 0, 1, 3, "neel", 32768),   # the 20x20 model, Neel-like samples
+    (1, 20, 20, 3, 128, 1, 1, 3, "neel", 500),
 ]
 
 
@@ -227,22 +223,17 @@ def test_local_energy_parity(P, geom, lx, ly, nl, d, prec, kind, B, spins, chunk
     print(f"eloc case {lx}x{ly} nl={nl} d={d} prec={prec} kind={kind} B={B} chunk={chunk}", flush=True)
     m, om, th, s = _case(P, geom, lx, ly, nl, d, prec, B, seed=7 + lx, spins=spins)
     oh = OH.Hamiltonian("tfim" if kind == 0 else "heisenberg", lx, ly, J=1.0, h=1.0)
-    ref = OH.local_energy(lambda c: OM.logpsi(th, c, om, bf16=(prec == 1)), oh, s)
+    ref = OH.local_energy(lambda c: OM.logpsi(th, c, om), oh, s)
     h = P.Hamiltonian(kind, lx, ly, J=1.0, h=1.0)
     e, st, lp = P.local_energy(m, torch.from_numpy(th).cuda(), h, torch.from_numpy(s).cuda(), chunk_seqs=chunk)
     e = e.cpu().numpy()
     st = st.cpu().numpy()
     rel = np.abs(e - ref) / np.maximum(np.abs(ref), 1.0)
     print(f"  max rel E_loc err {rel.max():.3e}; mean {st[0]:.6f} vs {ref.mean():.6f}")
-    assert rel.max() <= (1e-4 if prec == 0 else 5e-3)
+    assert rel.max() <= (1e-4 if prec == 0 else 1e-3)
     mean, var = OG.energy_stats(ref)
     assert abs(st[0] - mean) <= (1e-5 if prec == 0 else 1e-4) * max(1.0, abs(mean))
     assert abs(st[1] - var) <= (1e-4 if prec == 0 else 1e-3) * max(1.0, abs(var))
-    if prec == 1:
-        exact = OH.local_energy(lambda c: OM.logpsi(th, c, om), oh, s)
-        rel_x = np.abs(e - exact) / np.maximum(np.abs(exact), 1.0)
-        print(f"  BF16 vs exact float64 model: max rel E_loc err {rel_x.max():.3e}, mean {abs(e.mean() - exact.mean()):.3e}")
-        assert rel_x.max() <= 5e-2
     # statistics are exactly those of the returned E_loc (FP64 reduction)
     assert abs(st[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
 
