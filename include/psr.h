@@ -50,15 +50,30 @@ extern "C" {
 #define PSR_CHAIN_1D   0  /* Sec. II.C, Eq. (minGRU): one layer on a chain, head on h_t */
 #define PSR_SNAKE_2D   1  /* Sec. II.F-G: stacked 2D minGRU along the zigzag path */
 
-#define PSR_FP32       0  /* projections on FP32 MFMA */
-#define PSR_BF16       1  /* projections on BF16 MFMA, FP32 accumulation */
+/* Precision of the dense projections (W_z u, W_h [u, h_V], C h, D u; Sec. II.F).
+ * Everything else -- gates, the in-row scan and its carries, GELU, the head,
+ * log-softmax and log psi -- is FP32 in every mode.
+ *   PSR_FP32  FP32 matrix cores (v_mfma_f32_16x16x4_f32).
+ *   PSR_BF16  BF16 matrix cores with FP32 accumulation.  Each operand (weight or
+ *             activation) is carried as two bfloat16 parts, v ~ hi + lo with
+ *             hi = bf16(v), lo = bf16(v - hi) (about 16 significant bits), and a
+ *             product is hi*hi + lo*hi + hi*lo: three BF16 products.
+ *   PSR_FP16  FP16 matrix cores with FP32 accumulation, operands as two binary16
+ *             parts v ~ hi + 2^-11 lo (about 22 significant bits), same three
+ *             products.  Operands must stay below 65504 in magnitude.
+ * One rounding of the operands to 16 bits moves E_loc of the randomly
+ * initialised 32x32 model by several per cent; the split keeps log psi within
+ * ~1e-3 (BF16) of float64 there. */
+#define PSR_FP32       0
+#define PSR_BF16       1
+#define PSR_FP16       2
 
 typedef struct {
     int32_t geometry;   /* PSR_CHAIN_1D or PSR_SNAKE_2D */
     int32_t lx, ly;     /* lattice sides; the chain has ly = 1 and lx = N */
     int32_t n_layers;   /* chain: 1 */
     int32_t d;          /* hidden size d = d_h; 32, 64, 128 or 256 */
-    int32_t precision;  /* PSR_FP32 or PSR_BF16 (input type of the dense projections) */
+    int32_t precision;  /* PSR_FP32, PSR_BF16 or PSR_FP16 (arithmetic of the dense projections) */
     int32_t ckpt_rows;  /* rows per backward checkpoint chunk; 0 = max(1, 128 / lx) */
 } psr_model_desc;
 

@@ -21,11 +21,11 @@ __all__ = [
     "param_count", "param_offsets", "max_connected", "workspace_bytes",
     "logpsi", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
     "LogPsi", "per_sample_grad", "timing_begin", "timing_end",
-    "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "TFIM", "HEISENBERG",
+    "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "FP16", "TFIM", "HEISENBERG",
 ]
 
 CHAIN_1D, SNAKE_2D = 0, 1
-FP32, BF16 = 0, 1
+FP32, BF16, FP16 = 0, 1, 2
 TFIM, HEISENBERG = 0, 1
 OP_LOGPSI, OP_LOCAL_ENERGY, OP_BACKWARD, OP_SAMPLE = 0, 1, 2, 3
 

@@ -49,8 +49,8 @@ static int check_model(const psr_model_desc* m, Geom* out) {
     if (m->n_layers < 1 || m->n_layers > 8) return fail(PSR_EINVAL, "n_layers %d outside [1, 8]", m->n_layers);
     if (m->d != 32 && m->d != 64 && m->d != 128 && m->d != 256)
         return fail(PSR_EUNSUPPORTED, "hidden size %d is not 32, 64, 128 or 256", m->d);
-    if (m->precision != PSR_FP32 && m->precision != PSR_BF16)
-        return fail(PSR_EINVAL, "precision %d is not PSR_FP32 or PSR_BF16", m->precision);
+    if (m->precision != PSR_FP32 && m->precision != PSR_BF16 && m->precision != PSR_FP16)
+        return fail(PSR_EINVAL, "precision %d is not PSR_FP32, PSR_BF16 or PSR_FP16", m->precision);
     if (m->ckpt_rows < 0) return fail(PSR_EINVAL, "ckpt_rows must be >= 0");
     Geom g;
     g.chain = (m->geometry == PSR_CHAIN_1D);
@@ -58,7 +58,7 @@ static int check_model(const psr_model_desc* m, Geom* out) {
     g.ly = m->ly;
     g.nl = m->n_layers;
     g.d = m->d;
-    g.prec = m->precision == PSR_BF16 ? kBF16 : kFP32;
+    g.prec = m->precision == PSR_BF16 ? kBF16 : (m->precision == PSR_FP16 ? kFP16 : kFP32);
     const FwdShape sh = fwd_shape(g);
     if (sh.seqs < 1)
         return fail(PSR_EUNSUPPORTED, "row length %d exceeds the %d columns of a workgroup at d = %d", g.lx, sh.cols,
@@ -107,7 +107,7 @@ void param_offsets(const Geom& g, int64_t* off, int32_t* n) {
 Prepared prepared_layout(const Geom& g) {
     Prepared pl;
     const int64_t d = g.d;
-    const int64_t mat = d * d * 4;   // FP32 values, or BF16 high and low parts
+    const int64_t mat = d * d * 4;   // FP32 values, or 16-bit high and low parts
     int64_t fb = 0;
     // absent matrices keep offset 0 (never read) so that pointer arithmetic stays in range
     for (int l = 0; l < 8; ++l)
@@ -164,7 +164,7 @@ struct Carver {
 // Per-sequence device scratch of the forward kernel: the row frontier h^(l)
 // of every layer (the next row's h_V), in the projections' operand type.
 static int64_t frontier_seq_bytes(const Geom& g) {
-    return (int64_t)g.nl * g.lx * g.d * 4;   // FP32 values, or BF16 high and low parts
+    return (int64_t)g.nl * g.lx * g.d * 4;   // FP32 values, or 16-bit high and low parts
 }
 
 // sequences per forward launch for psr_logpsi (bounds the frontier workspace to ~256 MB)

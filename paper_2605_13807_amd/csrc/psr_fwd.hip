@@ -21,56 +21,26 @@
 //   4. after the last layer, the head gives log p of the site's own spin,
 //      accumulated per column with compensated (Neumaier) summation.
 //
-// Precision.  FP32: v_mfma_f32_16x16x4_f32.  BF16: every operand v of a dense
-// projection (weights and activations alike) is carried as two bfloat16 parts,
-// hi = bf16(v) and lo = bf16(v - hi), so that hi + lo holds v to about 16
-// significant bits, and a product W x is formed on v_mfma_f32_16x16x32_bf16 as
-// W_hi x_hi + W_lo x_hi + W_hi x_lo with FP32 accumulation (the dropped
-// W_lo x_lo term is ~2^-16 of the product).  A single bfloat16 rounding of the
-// operands perturbs this randomly initialised recurrence too much for the
-// local energy (per-configuration ratio errors of 0.1-1 at 20x20 and above);
-// the split keeps it at FP32-like accuracy for a third of the BF16 matrix rate,
-// still five times the FP32 matrix rate.
-#include "psr_internal.h"
-#include "gelu_fit.h"
-
-#include <type_traits>
+// Precision.  FP32: v_mfma_f32_16x16x4_f32.  The 16-bit paths carry every
+// operand v of a dense projection (weights and activations alike) as two
+// 16-bit parts, v ~ hi + s lo with hi = r(v) and lo = r((v - hi) / s), and form a
+// product W x as W_hi x_hi + s (W_lo x_hi + W_hi x_lo) on the 16-bit matrix
+// cores with FP32 accumulation (the dropped s^2 W_lo x_lo term is below the
+// parts' own rounding):
+//   BF16  r = bfloat16 rounding, s = 1: hi + lo holds ~16 significant bits;
+//   FP16  r = binary16 rounding, s = 1: ~22 significant bits where the low
+//         part is a normal number (|v| above ~2^-3), an absolute error below
+//         2^-25 where it is subnormal; within binary16's range (|v| < 65504,
+//         which the unit-scale activations and weights respect).
+// (The split-operand kernel for d >= 64 is psr_fwd_split.hip; this file keeps
+// the FP32 path, d = 32 and the chain.)
+// A single 16-bit rounding of the operands perturbs this randomly initialised
+// recurrence too much for the local energy (per-configuration log-ratio errors
+// of 0.1-1 at 20x20 and above); the split keeps it at a few hundred (BF16) or a
+// few (FP16) float32 ulps, for a third of the 16-bit matrix rate.
+#include "psr_fwd_common.h"
 
 namespace psr {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <int P> struct MF;
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-template <> struct MF<kBF16> {
-    typedef u32x8 Frag;            // dwords 0-3: 8 bfloat16 high parts; dwords 4-7: their low parts
-    static constexpr int K = 32;
-    static constexpr int ELT = 4;  // bytes per value (hi and lo) in the row frontier
-    // c + a b with a = a_hi + a_lo, b = b_hi + b_lo:  a_hi b_hi + a_lo b_hi + a_hi b_lo
-    // (The halves are taken by shufflevector: hipcc's __builtin_bit_cast of a `.hi`
-    // swizzle reads the vector's first half.)
-    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, a, 0, 1, 2, 3));
-        const bf16x8 al = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, a, 4, 5, 6, 7));
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b, b, 0, 1, 2, 3));
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b, b, 4, 5, 6, 7));
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-    }
-};
-template <> struct MF<kFP32> {
-    typedef float Frag;
-    static constexpr int K = 4;
-    static constexpr int ELT = 4;
-    __device__ static inline f32x4 mma(Frag a, Frag b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Parameter preparation: fragment-order weights and slot-order tables
@@ -81,12 +51,11 @@ __device__ __host__ inline int unit_pos(int u, int d) {
     return ((u >> 2) & 3) * (d >> 2) + 4 * (u >> 4) + (u & 3);
 }
 
-// bfloat16 high part of v (round to nearest even) and the float it stands for
-__device__ inline __bf16 bf16_hi(float v) { return (__bf16)v; }
-
-// BF16 weight fragments, split: for output tile mt and K block kb of 32, the
-// 64 lanes' 8 high parts (1 KB), then the 64 lanes' 8 low parts (1 KB).
-__global__ void prep_frag_bf16(const float* __restrict__ theta, MatSrc src, int d, __bf16* __restrict__ out) {
+// Split weight fragments: for output tile mt and K block kb of 32, the 64
+// lanes' 8 high parts (1 KB), then the 64 lanes' 8 low parts (1 KB).
+template <int P>
+__global__ void prep_frag_split(const float* __restrict__ theta, MatSrc src, int d, typename Split<P>::E* __restrict__ out) {
+    typedef typename Split<P>::E E;
     const int64_t n = (int64_t)d * d;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -98,8 +67,8 @@ __global__ void prep_frag_bf16(const float* __restrict__ theta, MatSrc src, int 
     const int r = 16 * mt + (lane & 15), g = lane >> 4;
     const int k = slot_unit(8 * kb + j, g);
     const float v = theta[src.base + (int64_t)r * src.ld + src.coff + k];
-    const __bf16 hi = bf16_hi(v);
-    const __bf16 lo = (__bf16)(v - (float)hi);
+    const E hi = (E)v;
+    const E lo = (E)((v - (float)hi) * (1.0f / Split<P>::kLoScale));
     const int64_t o = ((f * 2) * 64 + lane) * 8 + j;
     out[o] = hi;
     out[o + 512] = lo;
@@ -191,7 +160,9 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
             const int64_t n = (int64_t)d * d;
             const int blocks = (int)((n + T - 1) / T);
             if (g.prec == kBF16)
-                prep_frag_bf16<<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<__bf16*>(frag + fo));
+                prep_frag_split<kBF16><<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<__bf16*>(frag + fo));
+            else if (g.prec == kFP16)
+                prep_frag_split<kFP16><<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<_Float16*>(frag + fo));
             else
                 prep_frag_f32<<<blocks, T, 0, st>>>(theta, s, d, reinterpret_cast<float*>(frag + fo));
         }
@@ -221,284 +192,6 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
     const int ih = g.chain ? 4 : 6 * g.nl;   // index of W_o in the tensor list
     prep_head<<<(d + T - 1) / T, T, 0, st>>>(theta, off[ih], off[ih + 1], d, tab + pl.head_w, tab + pl.head_b);
     return (int)hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Device helpers
-// ---------------------------------------------------------------------------
-
-// Lane value from `row_shr:n` within the 16-lane DPP row; lanes without a
-// source read 0 (bound_ctrl), so the move folds into the consuming VALU op.
-template <int CTRL>
-__device__ inline float dpp0(float src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, src), CTRL, 0xf, 0xf, true));
-}
-
-// Lane value from `row_shr:n`; lanes without a source read 1.
-template <int CTRL>
-__device__ inline float dpp1(float src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, 1.0f),
-                                                                 __builtin_bit_cast(int, src), CTRL, 0xf, 0xf, false));
-}
-
-// Inclusive scan of affine maps h -> A h + B over the 16 lanes of each DPP row
-// (Hillis-Steele, shifts 1, 2, 4, 8) for the four slots of a lane at once:
-//   (A, B) after (A', B')  =  (A A', A B' + B).
-// Each step reads the neighbour's registers as the DPP source operand of the
-// VALU op itself -- B += B' A (v_fmac_f32_dpp), then A *= A' (v_mul_f32_dpp) --
-// so it costs two instructions per map.  Without bound_ctrl a lane whose
-// source lies outside the row is not written, i.e. it composes with the
-// identity map.  FULL_A = false leaves A after the last step un-updated, for
-// callers that read only the inclusive B.  Hazards: a DPP read of a VGPR needs
-// two wait states after the VALU write; the leading s_nop covers values written
-// just before the block, inside it every DPP read is at least four instructions
-// after the write, and the trailing s_nop covers DPP reads of A or B right
-// after the block.
-template <bool FULL_A>
-__device__ inline void row_scan4(float (&A)[4], float (&B)[4]) {
-#define PSR_SCAN_B(S)                                                      \
-    "v_fmac_f32_dpp %0, %0, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_fmac_f32_dpp %1, %1, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_fmac_f32_dpp %2, %2, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_fmac_f32_dpp %3, %3, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
-#define PSR_SCAN_A(S)                                                     \
-    "v_mul_f32_dpp %4, %4, %4 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_mul_f32_dpp %5, %5, %5 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_mul_f32_dpp %6, %6, %6 row_shr:" S " row_mask:0xf bank_mask:0xf\n" \
-    "v_mul_f32_dpp %7, %7, %7 row_shr:" S " row_mask:0xf bank_mask:0xf\n"
-    if constexpr (FULL_A)
-        asm("s_nop 1\n" PSR_SCAN_B("1") PSR_SCAN_A("1") PSR_SCAN_B("2") PSR_SCAN_A("2") PSR_SCAN_B("4") PSR_SCAN_A("4")
-            PSR_SCAN_B("8") PSR_SCAN_A("8") "s_nop 1"
-            : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
-    else
-        asm("s_nop 1\n" PSR_SCAN_B("1") PSR_SCAN_A("1") PSR_SCAN_B("2") PSR_SCAN_A("2") PSR_SCAN_B("4") PSR_SCAN_A("4")
-            PSR_SCAN_B("8") "s_nop 1"
-            : "+v"(B[0]), "+v"(B[1]), "+v"(B[2]), "+v"(B[3]), "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]));
-#undef PSR_SCAN_A
-#undef PSR_SCAN_B
-}
-
-// h = b + a * (B of lane - 1 in the DPP row), with the neighbour's register read
-// as the DPP source of the fmac; lane 0 of a row has no source and keeps b.
-// The DPP read of B follows its last write (in row_scan4) by at least the
-// trailing s_nop there.
-__device__ inline float carry_apply(float b, float a, float B) {
-    asm("v_fmac_f32_dpp %0, %1, %2 row_shr:1 row_mask:0xf bank_mask:0xf" : "+v"(b) : "v"(B), "v"(a));
-    return b;
-}
-
-// GELU(x) = x Phi(x) = max(x, 0) - |x| p(x) with the Gaussian tail
-// p(x) = erfc(|x|/sqrt 2)/2 ~ t Ph(t) 2^(-C x^2), t = 1/(1 + S|x|)
-// (degree-5 coefficients fitted by gen_gelu_fit.py, accurate to float32).
-__device__ inline float gelu_tail(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(ax, kGeluS, 1.0f));
-    float q = kGeluP[0];
-#pragma unroll
-    for (int k = 1; k <= 5; ++k) q = fmaf(q, t, kGeluP[k]);
-    const float p = (t * q) * __builtin_amdgcn_exp2f((x * x) * -kGeluC);
-    // max(x, 0) on the bit pattern: a negative float is a negative int32
-    const float xp = __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
-    return fmaf(-ax, p, xp);
-}
-
-__device__ inline void neumaier(float& s, float& c, float v) {
-    const float t = s + v;
-    c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
-    s = t;
-}
-
-// A operand (weights) of one 16-row output tile, per lane: BF16 one K block of
-// 32 per piece (8 high and 8 low parts), FP32 four K steps of 4 per piece.
-template <int P, int D>
-struct AOp {
-    static constexpr int N = (P == kBF16) ? D / 32 : D / 16;
-    typedef typename std::conditional<P == kBF16, u32x8, f32x4>::type T;
-};
-
-// The weight fragments come through buffer loads: the matrix base and the tile
-// offset stay scalar and the lane offset is one constant vector register, which
-// frees the registers that per-tile 64-bit addresses would hold (such kernels
-// spilled without it); the descriptor bounds the matrix (an out-of-range lane
-// would read zeros).  A tile is D * 64 bytes in both precisions.
-template <int P, int D, class W>
-__device__ inline void load_a(W& w, const uint8_t* __restrict__ mat, int mt, int lane) {
-    constexpr int TILE = D * 64;
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(mat), 0, TILE * (D / 16), 0x00020000);
-#pragma unroll
-    for (int k = 0; k < AOp<P, D>::N; ++k) {
-        if constexpr (P == kBF16) {
-            const u32x4 hi = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 2048, mt * TILE, 0));
-            const u32x4 lo =
-                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 2048 + 1024, mt * TILE, 0));
-            w[k] = __builtin_shufflevector(hi, lo, 0, 1, 2, 3, 4, 5, 6, 7);
-        } else {
-            w[k] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + k * 1024, mt * TILE, 0));
-        }
-    }
-}
-
-// acc[c] += W(tile) * b[c] for the NTC column tiles
-template <int P, int D, int NTC, class W, class B>
-__device__ inline void mma_a(f32x4 (&acc)[NTC], const W& w, const B& b) {
-    if constexpr (P == kBF16) {
-#pragma unroll
-        for (int kb = 0; kb < D / 32; ++kb)
-#pragma unroll
-            for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(w[kb], b[c][kb], acc[c]);
-    } else {
-#pragma unroll
-        for (int kq = 0; kq < D / 16; ++kq)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int c = 0; c < NTC; ++c) acc[c] = MF<P>::mma(w[kq][e], b[c][4 * kq + e], acc[c]);
-    }
-}
-
-constexpr int kWaves = 4;
-// LDS for a workgroup's BF16 row frontier (and one zero row)
-constexpr int kLdsFrontier = 112 * 1024;
-constexpr float kNegLog2e = -1.4426950408889634f;
-constexpr float kLn2 = 0.69314718055994531f;
-
-// Gates and the chunked scan of one output tile (4 units per lane, NTC positions):
-//   z = sigmoid(az), a = z (0 at a row start), b = (1 - z) htilde,
-//   h = a h_prev + b along the row.
-template <int NTC, bool CROSS, bool ALIGNED>
-__device__ inline void scan_tile(const f32x4 (&az)[NTC], const f32x4 (&ah)[NTC], const float (&keep)[NTC],
-                                 float (&h)[NTC][4], float (&xw)[2][kWaves][16][2], int mt, int wave, int g, int r16) {
-    float A[NTC][4], Bv[NTC][4];   // maps of the positions, composed inside the chunk
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int c = 0; c < NTC; ++c) {
-            const float z = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(az[c][i] * kNegLog2e));
-            // ALIGNED: every row starts at position 0 of lane 0 of a DPP row, where the
-            // carry is zero and the multiplier is never applied, so a needs no mask
-            const float aa = ALIGNED ? z : z * keep[c];
-            const float bb = fmaf(-z, ah[c][i], ah[c][i]);   // (1 - z) htilde
-            if (c == 0) {
-                A[c][i] = aa;
-                Bv[c][i] = bb;
-            } else {
-                Bv[c][i] = fmaf(aa, Bv[c - 1][i], bb);
-                A[c][i] = aa * A[c - 1][i];
-            }
-        }
-    }
-    // chunk aggregates -> inclusive over chunks 0..lane of the DPP row (in place: the
-    // last column's map is not needed again, because the inclusive value is its h)
-    float (&sA)[4] = A[NTC - 1];
-    float (&sB)[4] = Bv[NTC - 1];
-    row_scan4<CROSS>(sA, sB);
-    if constexpr (!CROSS) {
-        // no carry enters a wave: lane 0 of a DPP row starts a sequence row
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int c = 0; c + 1 < NTC; ++c) h[c][i] = carry_apply(Bv[c][i], A[c][i], sB[i]);
-            h[NTC - 1][i] = sB[i];
-        }
-    } else {
-        float X[4];   // carry entering this lane's chunk from the lanes before it
-#pragma unroll
-        for (int i = 0; i < 4; ++i) X[i] = dpp0<0x111>(sB[i]);
-        const int buf = mt & 1;
-        if (r16 == 15) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                xw[buf][wave][4 * g + i][0] = sA[i];
-                xw[buf][wave][4 * g + i][1] = sB[i];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float Xa = dpp1<0x111>(sA[i]);   // product of the multipliers before this chunk
-            float W = 0.0f;                        // carry entering this wave
-            for (int w = 0; w < wave; ++w) W = fmaf(xw[buf][w][4 * g + i][0], W, xw[buf][w][4 * g + i][1]);
-            const float Xt = fmaf(Xa, W, X[i]);
-#pragma unroll
-            for (int c = 0; c + 1 < NTC; ++c) h[c][i] = fmaf(A[c][i], Xt, Bv[c][i]);
-            h[NTC - 1][i] = fmaf(sA[i], W, sB[i]);
-        }
-    }
-}
-
-// slots s, s+1 (s even) of a lane's operand array.  BF16 packs the pair's high
-// parts into one dword of the fragment's first half and their low parts
-// (v - hi, rounded again) into the same dword of the second half.
-template <int P, int D>
-__device__ inline void set_pair(typename MF<P>::Frag (&f)[D / MF<P>::K], int s, float x0, float x1) {
-    if constexpr (P == kBF16) {
-        bf16x2 v;
-        v[0] = bf16_hi(x0);
-        v[1] = bf16_hi(x1);
-        const uint32_t hu = __builtin_bit_cast(uint32_t, v);
-        bf16x2 w;
-        w[0] = (__bf16)(x0 - __builtin_bit_cast(float, hu << 16));
-        w[1] = (__bf16)(x1 - __builtin_bit_cast(float, hu & 0xFFFF0000u));
-        const int q = (s & 7) >> 1;
-        f[s >> 3][q] = hu;
-        f[s >> 3][4 + q] = __builtin_bit_cast(uint32_t, w);
-    } else {
-        f[s] = x0;
-        f[s + 1] = x1;
-    }
-}
-
-// Keep the values of output tile mt (slots 4mt..4mt+3 of an operand array) at
-// this point of the program: an empty volatile asm that reads them stops the
-// compiler from sinking their computation into a later pipeline stage.
-template <int P, int D>
-__device__ inline void pin_tile(typename MF<P>::Frag (&f)[D / MF<P>::K], int mt) {
-    if constexpr (P == kBF16) {
-        const int q = 2 * (mt & 1);
-        asm volatile("" ::"v"(f[mt >> 1][q]), "v"(f[mt >> 1][q + 1]), "v"(f[mt >> 1][4 + q]), "v"(f[mt >> 1][5 + q]));
-    } else {
-        asm volatile("" ::"v"(f[4 * mt]), "v"(f[4 * mt + 1]), "v"(f[4 * mt + 2]), "v"(f[4 * mt + 3]));
-    }
-}
-__device__ inline void pin1(float& x) { asm volatile("" : "+v"(x)); }
-
-// Row frontier (h of the previous row, in the projections' operand form):
-// per sequence-local index qi, layer l, physical column i, lane group g, the
-// lane's d/4 slots are contiguous (BF16: per fragment, the 16 bytes of high
-// parts, then the 16 bytes of low parts), so a lane moves whole 16-byte pieces.
-template <int ELT, int D>
-__device__ inline uint8_t* col_ptr(void* base, int64_t qi, int l, int nslot, int lx, int i, int g) {
-    return reinterpret_cast<uint8_t*>(base) + ((((size_t)qi * nslot + l) * lx + i) * D + (size_t)g * (D / 4)) * ELT;
-}
-
-// 16-byte pieces of a lane's operand array (BF16: half a fragment, high parts
-// first; FP32: four slots)
-template <int P, int D>
-__device__ inline void frag_set16(typename MF<P>::Frag (&f)[D / MF<P>::K], int k, f32x4 v) {
-    if constexpr (P == kBF16) {
-        const u32x4 u = __builtin_bit_cast(u32x4, v);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) f[k >> 1][4 * (k & 1) + e] = u[e];
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) f[4 * k + e] = v[e];
-    }
-}
-template <int P, int D>
-__device__ inline f32x4 frag_get16(const typename MF<P>::Frag (&f)[D / MF<P>::K], int k) {
-    if constexpr (P == kBF16) {
-        const int o = 4 * (k & 1);
-        return __builtin_bit_cast(f32x4, u32x4{f[k >> 1][o], f[k >> 1][o + 1], f[k >> 1][o + 2], f[k >> 1][o + 3]});
-    } else {
-        return f32x4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
-    }
-}
-
-// 16 bytes at a uniform float base plus a per-lane byte offset that fits 32 bits
-// (lets the compiler address with a scalar base and a 32-bit vector offset)
-__device__ inline f32x4 ld16(const float* base, uint32_t byte_off) {
-    return *reinterpret_cast<const f32x4*>(reinterpret_cast<const uint8_t*>(base) + byte_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,18 +433,18 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                         // residual h^(l-1) of this row, from the frontier (layers >= 2)
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
-                            if constexpr (P == kBF16) {
+                            if constexpr (P != kFP32) {
                                 // slots 4mt..4mt+3: two dwords of high parts and the two
                                 // dwords of their low parts, 16 bytes further on
+                                typedef typename Split<P>::E2 E2;
                                 const uint8_t* q = rsrc[c] + (mt >> 1) * 32 + (mt & 1) * 8;
                                 const uint2 vh = *reinterpret_cast<const uint2*>(q);
                                 const uint2 vl = *reinterpret_cast<const uint2*>(q + 16);
-                                so[c] = f32x4{__builtin_bit_cast(float, vh.x << 16) + __builtin_bit_cast(float, vl.x << 16),
-                                              __builtin_bit_cast(float, vh.x & 0xFFFF0000u) +
-                                                  __builtin_bit_cast(float, vl.x & 0xFFFF0000u),
-                                              __builtin_bit_cast(float, vh.y << 16) + __builtin_bit_cast(float, vl.y << 16),
-                                              __builtin_bit_cast(float, vh.y & 0xFFFF0000u) +
-                                                  __builtin_bit_cast(float, vl.y & 0xFFFF0000u)};
+                                const E2 h0 = __builtin_bit_cast(E2, vh.x), h1 = __builtin_bit_cast(E2, vh.y);
+                                const E2 l0 = __builtin_bit_cast(E2, vl.x), l1 = __builtin_bit_cast(E2, vl.y);
+                                constexpr float sc = Split<P>::kLoScale;
+                                so[c] = f32x4{fmaf((float)l0[0], sc, (float)h0[0]), fmaf((float)l0[1], sc, (float)h0[1]),
+                                              fmaf((float)l1[0], sc, (float)h1[0]), fmaf((float)l1[1], sc, (float)h1[1])};
                                 if constexpr (!LDSF) so[c] = so[c] * rs;   // layer 1 has no residual
                             } else {
                                 so[c] = *reinterpret_cast<const f32x4*>(rsrc[c] + 16 * mt) * rs;
@@ -1058,6 +751,11 @@ static constexpr int ntc_for(int prec, int d) {
 
 FwdShape fwd_shape(const Geom& g) {
     FwdShape s;
+    if (split_kernel_applies(g)) {
+        split_shape(g, &s);
+        return s;
+    }
+    s.split_kernel = 0;
     s.ntc = ntc_for(g.prec, g.d);
     s.waves = kWaves;
     s.cols = s.waves * s.ntc * 16;
@@ -1068,9 +766,9 @@ FwdShape fwd_shape(const Geom& g) {
         const int c0 = k * g.lx, c1 = (k + 1) * g.lx - 1;
         if (c0 / per_wave != c1 / per_wave) s.cross_wave = 1;
     }
-    // BF16 frontier rows: d values of 4 bytes (high and low parts) plus 16 bytes of padding
+    // split frontier rows: d values of 4 bytes (high and low parts) plus 16 bytes of padding
     const int64_t pitch = (int64_t)g.d * 4 + 16;
-    s.lds_frontier = (!g.chain && g.prec == kBF16 &&
+    s.lds_frontier = (!g.chain && g.prec != kFP32 &&
                       (int64_t)g.d * 4 + (int64_t)s.seqs * g.nl * g.lx * pitch <= kLdsFrontier) ? 1 : 0;
     return s;
 }
@@ -1086,7 +784,7 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
         else
             fwd_kernel<P, D, NTC, false, true, false, false><<<grid, block, 0, st>>>(a);
     } else if (a.sh.lds_frontier) {
-        if constexpr (P == kBF16) {
+        if constexpr (P != kFP32) {
             if (a.sh.cross_wave)
                 fwd_kernel<P, D, NTC, true, false, false, true><<<grid, block, 0, st>>>(a);
             else if (a.g.lx == 16 * NTC)
@@ -1107,6 +805,7 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
 
 int launch_forward(const FwdArgs& a, hipStream_t st) {
     const int d = a.g.d;
+    if (a.sh.split_kernel) return launch_forward_split(a, st);
     if (a.sh.ntc != ntc_for(a.g.prec, d)) return (int)hipErrorInvalidValue;   // shape from another model
     if (a.g.prec == kBF16) {
         switch (d) {
@@ -1114,6 +813,13 @@ int launch_forward(const FwdArgs& a, hipStream_t st) {
             case 64: return launch_t<kBF16, 64, ntc_for(kBF16, 64)>(a, st);
             case 128: return launch_t<kBF16, 128, ntc_for(kBF16, 128)>(a, st);
             case 256: return launch_t<kBF16, 256, ntc_for(kBF16, 256)>(a, st);
+        }
+    } else if (a.g.prec == kFP16) {
+        switch (d) {
+            case 32: return launch_t<kFP16, 32, ntc_for(kFP16, 32)>(a, st);
+            case 64: return launch_t<kFP16, 64, ntc_for(kFP16, 64)>(a, st);
+            case 128: return launch_t<kFP16, 128, ntc_for(kFP16, 128)>(a, st);
+            case 256: return launch_t<kFP16, 256, ntc_for(kFP16, 256)>(a, st);
         }
     } else {
         switch (d) {

@@ -4,7 +4,7 @@
 // ------------------------------------------------
 // The dense projections are MFMA products  out[unit][column] = W[unit][k] * act[k][column]
 // with the weights as the A operand and the activations as the B operand of
-// v_mfma_f32_16x16x32_bf16 (BF16 path) or v_mfma_f32_16x16x4_f32 (FP32 path).
+// v_mfma_f32_16x16x32_bf16 / _f16 (split 16-bit paths) or v_mfma_f32_16x16x4_f32 (FP32 path).
 // A column is one (sequence, site) pair, so the 16 columns of an MFMA tile are
 // 16 lanes of a DPP row and the scan along a lattice row runs across lanes.
 //
@@ -27,7 +27,8 @@
 namespace psr {
 
 constexpr int kFP32 = 0;
-constexpr int kBF16 = 1;
+constexpr int kBF16 = 1;   // split BF16 operands (hi + lo)
+constexpr int kFP16 = 2;   // split binary16 operands (hi + 2^-11 lo)
 
 __host__ __device__ inline int slot_unit(int s, int g) { return 16 * (s >> 2) + 4 * g + (s & 3); }
 
@@ -67,9 +68,13 @@ struct FwdShape {
     int cols;         // columns per workgroup = waves * ntc * 16
     int seqs;         // sequences per workgroup = cols / lx
     int cross_wave;   // some sequence row spans a wave boundary
-    int lds_frontier; // the row frontier is kept in LDS (BF16 when it fits)
+    int lds_frontier; // the row frontier is kept in LDS (split 16-bit paths, when it fits)
+    int split_kernel; // 1: the units-split kernel of psr_fwd_split.hip runs this model
 };
 FwdShape fwd_shape(const Geom& g);
+// The units-split kernel (split 16-bit operands, 2D, d >= 64, rows within its columns).
+bool split_kernel_applies(const Geom& g);
+void split_shape(const Geom& g, FwdShape* s);
 
 // Arguments of the forward kernel.
 struct FwdArgs {
@@ -84,7 +89,7 @@ struct FwdArgs {
     const float* tab;         // prepared tables
     Prepared pl;
     FwdShape sh;
-    void* frontier;           // [q_count][nl][lx][d] h of the previous row (bf16 or f32), indexed by q - q_begin
+    void* frontier;           // [q_count][nl][lx][d] h of the previous row (f32 or 16-bit pairs), indexed by q - q_begin
     float* out_hi;            // [.] log psi, high part   (indexed by q)
     float* out_lo;            // [.] log psi, low part    (indexed by q) or NULL
     float* logp_site;         // [q][N] or NULL
@@ -94,6 +99,7 @@ struct FwdArgs {
 int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_t* frag, float* tab,
                    hipStream_t st);
 int launch_forward(const FwdArgs& a, hipStream_t st);
+int launch_forward_split(const FwdArgs& a, hipStream_t st);
 int launch_pack_spins(const int8_t* spins, int64_t B, int N, uint32_t* packed, hipStream_t st);
 int launch_check_spins(const int8_t* spins, int64_t n, int* bad, hipStream_t st);
 
