@@ -133,6 +133,21 @@ int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins,
                float* logpsi, float* logp_site, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * psr_logpsi without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The call allocates nothing: its scratch is a static
+ * device array of psr_static_scratch_bytes() bytes (64 MiB) that each GPU holds
+ * until the process ends.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads) race; the caller
+ * serialises them.  A batch whose workspace (psr_workspace_bytes(m,
+ * PSR_OP_LOGPSI, B, 0)) exceeds the array is rejected with PSR_ENOMEM before
+ * anything is queued.  Arguments and results otherwise as psr_logpsi.
+ */
+int64_t psr_static_scratch_bytes(void);
+int psr_logpsi_static(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B,
+                      float* logpsi, float* logp_site, void* stream);
+
+/*
  * Connected configurations of each sample (Sec. II.A: the extra forward passes
  * of the local energy), in canonical order: sites ascending; at each site a the
  * bond (a, a+1) before the bond (a, a+lx).  Heisenberg: one entry per bond

@@ -19,7 +19,7 @@ import torch
 __all__ = [
     "Model", "Hamiltonian", "PsrError", "lib",
     "param_count", "param_offsets", "max_connected", "workspace_bytes",
-    "logpsi", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
+    "logpsi", "logpsi_static", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
     "LogPsi", "per_sample_grad", "timing_begin", "timing_end",
     "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "FP16", "TFIM", "HEISENBERG",
 ]
@@ -125,6 +125,10 @@ def lib() -> ctypes.CDLL:
         L.psr_workspace_bytes.restype = i64
         L.psr_logpsi.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp, sz, vp]
         L.psr_logpsi.restype = ctypes.c_int
+        L.psr_logpsi_static.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp]
+        L.psr_logpsi_static.restype = ctypes.c_int
+        L.psr_static_scratch_bytes.argtypes = []
+        L.psr_static_scratch_bytes.restype = i64
         L.psr_connected.argtypes = [P(_HamDesc), vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.psr_connected.restype = ctypes.c_int
         L.psr_local_energy.argtypes = [P(_ModelDesc), vp, P(_HamDesc), vp, i64, i64, vp, vp, vp, vp, sz, vp]
@@ -220,6 +224,19 @@ def logpsi(m: Model, theta: torch.Tensor, spins: torch.Tensor, site_logp: bool =
         ws = _workspace(m, OP_LOGPSI, B, spins.device)
     _check(lib().psr_logpsi(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps), _ptr(ws),
                             ws.numel(), _stream(spins.device)))
+    return (out, lps) if site_logp else out
+
+
+def logpsi_static(m: Model, theta: torch.Tensor, spins: torch.Tensor, site_logp: bool = False):
+    """log psi through psr_logpsi_static: no workspace, the library's static device scratch
+    (calls on one GPU must not overlap)."""
+    theta = _dev(theta, torch.float32, "theta")
+    spins = _dev(spins, torch.int8, "spins")
+    B = spins.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=spins.device)
+    lps = torch.empty(B, m.n_sites, dtype=torch.float32, device=spins.device) if site_logp else None
+    _check(lib().psr_logpsi_static(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps),
+                                   _stream(spins.device)))
     return (out, lps) if site_logp else out
 
 

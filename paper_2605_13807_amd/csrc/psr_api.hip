@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -325,6 +326,35 @@ static int run_forward(const Geom& g, const Prepared& pl, const uint32_t* packed
     return e;
 }
 
+// ---------------------------------------------------------------------------
+// Static device scratch of psr_logpsi_static (callers that cannot allocate)
+// ---------------------------------------------------------------------------
+
+// Each GPU the library runs on holds one copy of this array until the process
+// ends.  Host code must not pass its name to a kernel (that is a host-side
+// stand-in, not a device address): its address on the current device comes
+// from hipGetSymbolAddress, once per device, below.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;   // per device, filled on the first call on that device
+
+static int static_scratch(void** out) {
+    int dev = 0;
+    int r = dev_check((int)hipGetDevice(&dev), "current device");
+    if (r) return r;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((r = dev_check((int)hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "static scratch address"))) return r;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PSR_OK;
+}
+
 }  // namespace psr
 
 using namespace psr;
@@ -447,6 +477,27 @@ int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins,
     }
     if ((r = dev_check(launch_combine_logpsi(w.hi, w.lo, B, logpsi, st), "combine"))) return r;
     return ok();
+}
+
+int64_t psr_static_scratch_bytes(void) { return (int64_t)kStaticScratchBytes; }
+
+int psr_logpsi_static(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
+                      float* logp_site, void* stream) {
+    Geom g;
+    int r = check_model(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    LogpsiWs w;
+    const int64_t need = carve_logpsi(g, B, nullptr, &w);
+    if (need > (int64_t)kStaticScratchBytes)
+        return fail(PSR_ENOMEM, "a batch of %lld needs %lld bytes of scratch; the static scratch holds %lld",
+                    (long long)B, (long long)need, (long long)kStaticScratchBytes);
+    void* ws = nullptr;
+    if ((r = static_scratch(&ws))) return r;
+    // every region of the scratch is written before it is read (packed spins,
+    // prepared weights, frontier rows, log psi halves): nothing to clear
+    return psr_logpsi(m, theta, spins, B, logpsi, logp_site, ws, kStaticScratchBytes, stream);
 }
 
 int psr_connected(const psr_hamiltonian* H, const int8_t* spins, int64_t B, int64_t max_conn, int8_t* conn,

@@ -174,3 +174,20 @@ def test_lru_local_energy_host_checks(P):
                                   None) == -3
     assert L.psr_lru_local_energy(ctypes.byref(m), None, ctypes.byref(h_ok), None, 0, None, None, None, None, 0,
                                   None) == 0
+
+
+def test_logpsi_static_limits_on_host(P):
+    """The allocation-free entry point states its scratch size and rejects a batch
+    whose workspace exceeds it on the host, before touching a GPU."""
+    L = P.lib()
+    cap = L.psr_static_scratch_bytes()
+    assert cap == 64 << 20
+    m = P.Model(P.SNAKE_2D, 52, 52, 4, 256, P.BF16)
+    big = 4096
+    assert P.workspace_bytes(m, P.OP_LOGPSI, big) > cap
+    d = m.c()
+    code = L.psr_logpsi_static(ctypes.byref(d), ctypes.c_void_p(16), ctypes.c_void_p(16), big,
+                               ctypes.c_void_p(16), None, None)
+    assert code == -3
+    assert b"static scratch" in L.psr_last_error()
+    assert L.psr_logpsi_static(ctypes.byref(d), None, None, 0, None, None, None) == 0
