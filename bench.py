@@ -47,13 +47,13 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # HBM traffic of the forward kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by the same counters on a plain device copy of known size; valid only
 # for the kernel source it was measured on (its SHA-256 is recorded with it).
-# d = 256 runs the units-split kernel (psr_fwd_split.hip), smaller widths psr_fwd.hip.
+# The split paths at d = 128 and 256 run the units-split kernel (psr_fwd_split.hip).
 CSRC = os.path.join(ROOT, "paper_2605_13807_amd", "csrc")
 TRAFFIC = {
     "heisenberg52x52": (os.path.join(ROOT, "profiles", "fwd_split_kernel_heisenberg52x52_traffic.md"),
                         ["psr_fwd_split.hip", "psr_fwd_common.h"]),
-    "heisenberg32x32": (os.path.join(ROOT, "profiles", "fwd_kernel_heisenberg32x32_traffic.md"),
-                        ["psr_fwd.hip", "psr_fwd_common.h"]),
+    "heisenberg32x32": (os.path.join(ROOT, "profiles", "fwd_split_kernel_heisenberg32x32_traffic.md"),
+                        ["psr_fwd_split.hip", "psr_fwd_common.h"]),
 }
 
 PEAK = {  # MI355X datasheet peaks (dense)
@@ -231,7 +231,7 @@ def main() -> int:
         peak = PEAK["fp32_tflops"] if prec_ == P.FP32 else PEAK["bf16_tflops"]
         rf = {
             "bound": "mfma",
-            "kernel": "fwd_split_kernel" if (prec_ != P.FP32 and d >= 256) else "fwd_kernel",
+            "kernel": "fwd_split_kernel" if (prec_ != P.FP32 and d >= 128) else "fwd_kernel",
             "achieved": round(achieved, 2),
             "peak": peak,
             "unit": "TFLOP/s",

@@ -32,8 +32,8 @@
 //         part is a normal number (|v| above ~2^-3), an absolute error below
 //         2^-25 where it is subnormal; within binary16's range (|v| < 65504,
 //         which the unit-scale activations and weights respect).
-// (The split-operand kernel for d >= 64 is psr_fwd_split.hip; this file keeps
-// the FP32 path, d = 32 and the chain.)
+// (The split-operand kernel for d = 128 and 256 is psr_fwd_split.hip; this file
+// keeps the FP32 path, the split paths at d = 32 and 64, and the chain.)
 // A single 16-bit rounding of the operands perturbs this randomly initialised
 // recurrence too much for the local energy (per-configuration log-ratio errors
 // of 0.1-1 at 20x20 and above); the split keeps it at a few hundred (BF16) or a

@@ -1,5 +1,5 @@
 // Forward kernel of the split 16-bit paths (BF16 or FP16 operand pairs, see
-// psr_fwd.hip) for the stacked 2D snake minGRU (Sec. II.F-G) at d >= 64.
+// psr_fwd.hip) for the stacked 2D snake minGRU (Sec. II.F-G) at d = 128 and 256.
 //
 // The workgroup's W waves share its C = 16 NTC columns (a column is one site
 // of the current row of one sequence; whole sequence rows are packed back to
@@ -30,9 +30,10 @@
 
 namespace psr {
 
-// Waves and column tiles of the split kernel for width d.
-static constexpr int split_waves(int d) { return d >= 128 ? 8 : 4; }
-static constexpr int split_ntc(int d) { return d >= 256 ? 4 : 8; }
+// Waves and column tiles of the split kernel for width d (measured: at d = 128 four
+// waves of two tiles over 64 columns ran 14 % faster than eight waves over 64 or 128).
+static constexpr int split_waves(int d) { return d >= 256 ? 8 : 4; }
+static constexpr int split_ntc(int d) { return d >= 128 ? 4 : 8; }
 
 // One K block of 32 of output tile mt of a prepared split matrix: high parts in
 // dwords 0-3, low parts in dwords 4-7 (layout of prep_frag_split).
@@ -119,7 +120,10 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
     __shared__ float lsum[C][2];         // per-column Neumaier sum of log p (and its compensation)
     __shared__ float xw_unused[2][kWaves][16][2];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wave index through readfirstlane: the compiler then knows it is uniform, so the
+    // tile offsets of the weight loads stay scalar (no per-lane waterfall around the loads)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, r16 = lane & 15;
     const Geom G = a.g;
     const int lx = G.lx, ly = G.ly, nl = G.nl;
@@ -429,11 +433,10 @@ static int launch_split_t(const FwdArgs& a, hipStream_t st) {
     return (int)hipGetLastError();
 }
 
-// d = 256 only: at d <= 128 the lane-owns-all-units kernel of psr_fwd.hip measured faster
-// (its four register-resident operand sets fit there, and 32 columns per wave amortise
-// its weight reads)
+// d >= 128 (d = 64 keeps the lane-owns-all-units kernel of psr_fwd.hip, whose operand
+// sets fit in registers there; not measured with this kernel)
 bool split_kernel_applies(const Geom& g) {
-    return g.prec != kFP32 && !g.chain && g.d >= 256 && g.lx <= 16 * split_ntc(g.d);
+    return g.prec != kFP32 && !g.chain && g.d >= 128 && g.lx <= 16 * split_ntc(g.d);
 }
 
 void split_shape(const Geom& g, FwdShape* s) {
@@ -449,13 +452,11 @@ void split_shape(const Geom& g, FwdShape* s) {
 int launch_forward_split(const FwdArgs& a, hipStream_t st) {
     if (a.g.prec == kBF16) {
         switch (a.g.d) {
-            case 64: return launch_split_t<kBF16, 64>(a, st);
             case 128: return launch_split_t<kBF16, 128>(a, st);
             case 256: return launch_split_t<kBF16, 256>(a, st);
         }
     } else if (a.g.prec == kFP16) {
         switch (a.g.d) {
-            case 64: return launch_split_t<kFP16, 64>(a, st);
             case 128: return launch_split_t<kFP16, 128>(a, st);
             case 256: return launch_split_t<kFP16, 256>(a, st);
         }

@@ -72,7 +72,7 @@ struct FwdShape {
     int split_kernel; // 1: the units-split kernel of psr_fwd_split.hip runs this model
 };
 FwdShape fwd_shape(const Geom& g);
-// The units-split kernel (split 16-bit operands, 2D, d >= 64, rows within its columns).
+// The units-split kernel (split 16-bit operands, 2D, d = 128 or 256, rows within its columns).
 bool split_kernel_applies(const Geom& g);
 void split_shape(const Geom& g, FwdShape* s);
 

@@ -159,10 +159,12 @@ LOGPSI_CASES = [
     (1, 52, 52, 4, 256, 2, 2),
     (1, 60, 3, 4, 256, 2, 3),
     (1, 64, 2, 2, 64, 2, 5),
-    # the units-split kernel (d = 256) at other shapes: one sequence of 40 columns per
-    # workgroup, 4 sequences of 13 columns, ragged last workgroups
+    # the units-split kernel (d = 128, 256) at other shapes: one sequence of 40 columns
+    # per workgroup, 4 sequences of 13 columns, ragged last workgroups
     (1, 40, 3, 3, 256, 1, 7),
     (1, 13, 5, 2, 256, 2, 23),
+    (1, 20, 4, 3, 128, 2, 11),     # d = 128: 3 sequences of 20 in 64 columns
+    (1, 64, 2, 3, 128, 1, 3),      # d = 128: one 64-column row
 ]
 
 
