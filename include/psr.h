@@ -231,10 +231,13 @@ int psr_gradient_estimate(const float* O, int64_t B, int64_t P, const double* w,
 int psr_sample(const psr_model_desc* m, const float* theta, const float* uniforms, int64_t B,
                int8_t* spins, float* logpsi, void* ws, size_t ws_bytes, void* stream);
 
-/* Synchronous check of a spin batch: PSR_OK if every value is 0 or 1, PSR_EDATA otherwise. */
-int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream);
+/* Synchronous check of a spin batch: PSR_OK if every value is 0 or 1, PSR_EDATA otherwise.
+ *   spins  device int8[n_values]
+ *   flag   device int32[1], caller-owned scratch (overwritten; the call allocates nothing)
+ * The call queues the check on `stream` and waits for it. */
+int psr_check_spins(const int8_t* spins, int64_t n_values, int32_t* flag, void* stream);
 
-/* ---- 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.E) -- */
+/* ---- 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.G) -- */
 
 typedef struct {
     int32_t n;          /* chain length N, 1 .. 16384 */

@@ -1,6 +1,6 @@
 """Oracle: the 1D LRU ansatz -- TEST INFRASTRUCTURE (see ``oracle/__init__``).
 
-The paper's 1D model (Sec. II.B, Eq. (lru); Sec. II.E residual with GLU;
+The paper's 1D model (Sec. II.B, Eq. (lru); Sec. II.G residual with GLU;
 3 layers, d = d_h = 64 in Table I).  Per layer l with input sequence x_t in R^d:
 
     lambda = exp(-e^nu + i e^theta)                    (complex, per hidden unit)

@@ -104,6 +104,7 @@ class LruModel:
 
 
 _lib = None
+_flags: dict = {}   # per device: the int32 flag psr_check_spins writes
 
 
 def lib() -> ctypes.CDLL:
@@ -151,7 +152,7 @@ def lib() -> ctypes.CDLL:
         L.psr_lru_eloc_workspace_bytes.restype = i64
         L.psr_lru_local_energy.argtypes = [P(_LruDesc), vp, P(_HamDesc), vp, i64, vp, vp, vp, vp, sz, vp]
         L.psr_lru_local_energy.restype = ctypes.c_int
-        L.psr_check_spins.argtypes = [vp, i64, vp]
+        L.psr_check_spins.argtypes = [vp, i64, vp, vp]
         L.psr_check_spins.restype = ctypes.c_int
         L.psr_timing_begin.argtypes = []
         L.psr_timing_begin.restype = ctypes.c_int
@@ -395,9 +396,12 @@ def vmc_weights(eloc: torch.Tensor, stats: torch.Tensor) -> torch.Tensor:
 
 
 def check_spins(spins: torch.Tensor) -> None:
-    """Raise PsrError (PSR_EDATA) if any value is not 0 or 1 (synchronous)."""
+    """Raise PsrError (code PSR_EDATA) unless every value is 0 or 1 (synchronous)."""
     spins = _dev(spins, torch.int8, "spins")
-    _check(lib().psr_check_spins(_ptr(spins), spins.numel(), _stream(spins.device)))
+    key = spins.device.index
+    if key not in _flags:
+        _flags[key] = torch.zeros(1, dtype=torch.int32, device=spins.device)
+    _check(lib().psr_check_spins(_ptr(spins), spins.numel(), _ptr(_flags[key]), _stream(spins.device)))
 
 
 def timing_begin() -> None:

@@ -690,7 +690,7 @@ int psr_lru_logpsi(const psr_lru_desc* m, const float* theta, const int8_t* spin
     hipStream_t st = as_stream(stream);
     hipEvent_t stop;
     timing_before(st, &stop);
-    const int e = launch_lru_logpsi(g, theta, spins, B, logpsi, logp_site, static_cast<float*>(ws), st);
+    const int e = launch_lru_logpsi(g, theta, spins, B, logpsi, nullptr, logp_site, static_cast<float*>(ws), st);
     if (stop && hipEventRecord(stop, st) != hipSuccess) --g_tm.used;   // drop the half-recorded pair
     if ((r = dev_check(e, "LRU forward"))) return r;
     return ok();
@@ -704,8 +704,8 @@ struct LruElocWs {
     uint32_t* desc;
     float* mel;
     int8_t* conn;
-    float* lps;
-    float* lpc;
+    float *lps, *lps_lo;
+    float *lpc, *lpc_lo;
     float* scratch;
 };
 
@@ -723,7 +723,9 @@ static int64_t carve_lru_eloc(const LruGeom& g, int64_t B, int64_t mc, void* bas
     w->mel = reinterpret_cast<float*>(take(M * 4));
     w->conn = reinterpret_cast<int8_t*>(take(M * g.n));
     w->lps = reinterpret_cast<float*>(take(B * 4));
+    w->lps_lo = reinterpret_cast<float*>(take(B * 4));
     w->lpc = reinterpret_cast<float*>(take(M * 4));
+    w->lpc_lo = reinterpret_cast<float*>(take(M * 4));
     const int64_t sc = lru_workspace_floats(g, M > B ? M : B);
     w->scratch = reinterpret_cast<float*>(take(sc * 4));
     return o;
@@ -777,12 +779,14 @@ int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_ha
     for (int pass = 0; pass < 2; ++pass) {
         hipEvent_t stop;
         timing_before(st, &stop);
-        const int e = pass == 0 ? launch_lru_logpsi(g, theta, spins, B, w.lps, nullptr, w.scratch, st)
-                                : launch_lru_logpsi(g, theta, w.conn, M, w.lpc, nullptr, w.scratch, st);
+        const int e = pass == 0 ? launch_lru_logpsi(g, theta, spins, B, w.lps, w.lps_lo, nullptr, w.scratch, st)
+                                : launch_lru_logpsi(g, theta, w.conn, M, w.lpc, w.lpc_lo, nullptr, w.scratch, st);
         if (stop && hipEventRecord(stop, st) != hipSuccess) --g_tm.used;
         if ((r = dev_check(e, "LRU forward"))) return r;
     }
-    if ((r = dev_check(launch_lru_eloc_combine(B, mc, w.n_conn, w.diag, w.mel, w.lpc, w.lps, eloc, st), "E_loc")))
+    if ((r = dev_check(launch_lru_eloc_combine(B, mc, w.n_conn, w.diag, w.mel, w.lpc, w.lpc_lo, w.lps, w.lps_lo, eloc,
+                                               st),
+                       "E_loc")))
         return r;
     if ((r = dev_check(launch_stats(eloc, B, stats, st), "stats"))) return r;
     if (logpsi && (r = dev_check(hipMemcpyAsync(logpsi, w.lps, B * sizeof(float), hipMemcpyDeviceToDevice, st),
@@ -791,19 +795,15 @@ int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_ha
     return ok();
 }
 
-int psr_check_spins(const int8_t* spins, int64_t n_values, void* stream) {
+int psr_check_spins(const int8_t* spins, int64_t n_values, int32_t* flag, void* stream) {
     if (n_values < 0) return fail(PSR_EINVAL, "negative size");
     if (n_values == 0) return ok();
-    if (!spins) return fail(PSR_EINVAL, "spins must not be NULL");
-    int* bad = nullptr;
-    int r;
-    if ((r = dev_check((int)hipMalloc(&bad, sizeof(int)), "allocate flag"))) return r;
+    if (!spins || !flag) return fail(PSR_EINVAL, "spins and flag must not be NULL");
     hipStream_t st = as_stream(stream);
     int host = 0;
-    r = dev_check(launch_check_spins(spins, n_values, bad, st), "check");
-    if (!r) r = dev_check((int)hipMemcpyAsync(&host, bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
+    int r = dev_check(launch_check_spins(spins, n_values, flag, st), "check");
+    if (!r) r = dev_check((int)hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
     if (!r) r = dev_check((int)hipStreamSynchronize(st), "synchronise");
-    (void)hipFree(bad);   // cleanup; the status that matters is r
     if (r) return r;
     if (host) return fail(PSR_EDATA, "spins outside {0, 1}");
     return ok();

@@ -44,7 +44,7 @@ __global__ void check_kernel(const int8_t* __restrict__ s, int64_t n, int* bad) 
     if (__any(local) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-int launch_check_spins(const int8_t* spins, int64_t n, int* bad, hipStream_t st) {
+int launch_check_spins(const int8_t* spins, int64_t n, int32_t* bad, hipStream_t st) {
     const hipError_t me = hipMemsetAsync(bad, 0, sizeof(int), st);
     if (me != hipSuccess) return (int)me;
     if (n > 0) check_kernel<<<1024, 256, 0, st>>>(spins, n, bad);

@@ -101,7 +101,7 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
 int launch_forward(const FwdArgs& a, hipStream_t st);
 int launch_forward_split(const FwdArgs& a, hipStream_t st);
 int launch_pack_spins(const int8_t* spins, int64_t B, int N, uint32_t* packed, hipStream_t st);
-int launch_check_spins(const int8_t* spins, int64_t n, int* bad, hipStream_t st);
+int launch_check_spins(const int8_t* spins, int64_t n, int32_t* bad, hipStream_t st);
 
 // Hamiltonian descriptor as seen by the kernels.
 struct Ham {
@@ -155,10 +155,12 @@ __host__ __device__ inline int64_t lru_layer_floats(const LruGeom& g) {
 }
 int64_t lru_param_count(const LruGeom& g);
 int64_t lru_workspace_floats(const LruGeom& g, int64_t B);
+// logpsi_lo (or NULL): the low part of log psi (the FP64 sum as a float pair)
 int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
-                      float* logp_site, float* scratch, hipStream_t st);
-// E_loc from per-sample connected slots (s * max_conn + k) and the two log psi arrays
+                      float* logpsi_lo, float* logp_site, float* scratch, hipStream_t st);
+// E_loc from per-sample connected slots (s * max_conn + k) and the two log psi (hi, lo) arrays
 int launch_lru_eloc_combine(int64_t B, int64_t max_conn, const int32_t* n_conn, const float* diag, const float* mel,
-                            const float* lpc, const float* lps, double* eloc, hipStream_t st);
+                            const float* lpc, const float* lpc_lo, const float* lps, const float* lps_lo, double* eloc,
+                            hipStream_t st);
 
 }  // namespace psr

@@ -1,4 +1,4 @@
-// log psi of the 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.E).
+// log psi of the 1D LRU ansatz (Sec. II.B, Eq. (lru); residual with GLU, Sec. II.G).
 //
 // Per layer, with the layer input x_t in R^d at every site t of the chain:
 //   lambda = exp(-e^nu + i e^theta),  h_t = lambda h_{t-1} + e^gamma (B x_t),  h_{-1} = 0,
@@ -46,7 +46,8 @@ struct LruArgs {
     int64_t B;
     int S;                 // sequences per group
     int64_t groups;
-    float* logpsi;         // [B]
+    float* logpsi;         // [B] (log psi, or its high part when logpsi_lo is set)
+    float* logpsi_lo;      // [B] low part (log psi = hi + lo, the sum kept in FP64) or null
     float* logp_site;      // [B][N] or null
     float* scratch;
     int64_t per_wg;        // floats of workspace per workgroup
@@ -485,31 +486,41 @@ __global__ void __launch_bounds__(kThreads) lru_kernel(const LruArgs a) {
                 if (tid < w) red[tid] += red[tid + w];
                 __syncthreads();
             }
-            if (tid == 0 && q0 < a.B) a.logpsi[q0] = (float)(0.5 * red[0]);
+            if (tid == 0 && q0 < a.B) {
+                const float hi = (float)(0.5 * red[0]);
+                a.logpsi[q0] = hi;
+                if (a.logpsi_lo) a.logpsi_lo[q0] = (float)(0.5 * red[0] - (double)hi);
+            }
         } else if (tid < S && q0 + tid < a.B) {
             double acc = 0.0;
             for (int t = 0; t < N; ++t) acc += (double)GL[tid * N + t];
-            a.logpsi[q0 + tid] = (float)(0.5 * acc);
+            const float hi = (float)(0.5 * acc);
+            a.logpsi[q0 + tid] = hi;
+            if (a.logpsi_lo) a.logpsi_lo[q0 + tid] = (float)(0.5 * acc - (double)hi);
         }
         __syncthreads();   // the next group overwrites the workspace
     }
 }
 
 // E_loc(s) = diag(s) + sum_{k < n_conn(s)} mel(s, k) exp(log psi(sigma'_k) - log psi(sigma_s))
-// with the connected entries in per-sample slots (s * max_conn + k).  One wave per
-// sample, FP64 accumulation in a fixed order.
+// with the connected entries in per-sample slots (s * max_conn + k).  Both log psi
+// are (hi, lo) pairs of FP64 sums, so the prefix a flip leaves unchanged (bitwise
+// equal site terms) cancels in the difference.  One wave per sample, FP64
+// accumulation in a fixed order.
 __global__ void lru_eloc_kernel(int64_t B, int64_t max_conn, const int32_t* __restrict__ n_conn,
                                 const float* __restrict__ diag, const float* __restrict__ mel,
-                                const float* __restrict__ lpc, const float* __restrict__ lps,
+                                const float* __restrict__ lpc, const float* __restrict__ lpc_lo,
+                                const float* __restrict__ lps, const float* __restrict__ lps_lo,
                                 double* __restrict__ eloc) {
     const int lane = threadIdx.x & 63;
     const int64_t s = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (s >= B) return;
     const int64_t base = s * max_conn;
     const int nc = n_conn[s];
-    const double l0 = (double)lps[s];
+    const double l0 = (double)lps[s] + (double)lps_lo[s];
     double acc = 0.0;
-    for (int k = lane; k < nc; k += 64) acc += (double)mel[base + k] * exp((double)lpc[base + k] - l0);
+    for (int k = lane; k < nc; k += 64)
+        acc += (double)mel[base + k] * exp(((double)lpc[base + k] - l0) + (double)lpc_lo[base + k]);
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) eloc[s] = (double)diag[s] + acc;
 }
@@ -544,14 +555,16 @@ int64_t lru_workspace_floats(const LruGeom& g, int64_t B) {
 }
 
 int launch_lru_eloc_combine(int64_t B, int64_t max_conn, const int32_t* n_conn, const float* diag, const float* mel,
-                            const float* lpc, const float* lps, double* eloc, hipStream_t st) {
+                            const float* lpc, const float* lpc_lo, const float* lps, const float* lps_lo, double* eloc,
+                            hipStream_t st) {
     if (B == 0) return 0;
-    lru_eloc_kernel<<<(unsigned)((B + 3) / 4), 256, 0, st>>>(B, max_conn, n_conn, diag, mel, lpc, lps, eloc);
+    lru_eloc_kernel<<<(unsigned)((B + 3) / 4), 256, 0, st>>>(B, max_conn, n_conn, diag, mel, lpc, lpc_lo, lps, lps_lo,
+                                                             eloc);
     return (int)hipGetLastError();
 }
 
 int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
-                      float* logp_site, float* scratch, hipStream_t st) {
+                      float* logpsi_lo, float* logp_site, float* scratch, hipStream_t st) {
     if (B == 0) return 0;
     LruArgs a;
     a.g = g;
@@ -561,6 +574,7 @@ int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins,
     a.S = lru_seqs_per_group(g);
     a.groups = (B + a.S - 1) / a.S;
     a.logpsi = logpsi;
+    a.logpsi_lo = logpsi_lo;
     a.logp_site = logp_site;
     a.scratch = scratch;
     a.per_wg = lru_per_wg_floats(g);

@@ -55,6 +55,13 @@ def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, l
     ``lr`` is a constant or a function of the step index t = 0, 1, ... (e.g.
     ``lr_decay(eta0, delta0)``).  The uniforms of the sampler come from a seeded
     torch generator on the device, so a run is reproducible for a given seed.
+
+    Precision: the sampler and the backward run in FP32 whatever ``m.precision``
+    is; only the local energies follow it.  The 16-bit paths split every
+    projection operand into two parts (about 16 bits for BF16, 22 for FP16), so
+    their E_loc stays within 1e-3 of the float64 model on the benchmark lattices
+    (and within ~1e-5 at the small lattices a VMC run here trains) and the
+    estimator pairs it with the gradient of the same model up to that error.
     """
     dev = theta.device
     gen = torch.Generator(device=dev)

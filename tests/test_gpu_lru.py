@@ -126,6 +126,7 @@ ELOC_CASES = [
     ("tfim", 10, 2, 16, 16, 20),
     ("heisenberg", 9, 1, 32, 32, 15),
     ("tfim", 64, 3, 64, 64, 6),
+    ("tfim", 256, 3, 64, 64, 2),      # the Table I model at N = 256: ratios of log psi ~ 180
 ]
 
 
