@@ -11,13 +11,16 @@ and imports nothing from it; the two meet only through the seeded inputs of
 Modules
 -------
 ``model``        geometry, parameter layout, the 1D minGRU chain and the 2D
-                 snake minGRU, log psi by the sequential recurrence (authority)
-                 and by an independent Blelloch scan over each row.
+                 snake minGRU (single sites or 2x2 patches), log psi by the
+                 sequential recurrence (authority) and by an independent
+                 Blelloch scan over each row.
 ``hamiltonian``  TFIM and (Marshall-rotated) Heisenberg: canonical connected
                  configurations, matrix elements, diagonal part, E_loc, dense
                  Hamiltonians from Pauli Kronecker products, exact spectra.
 ``sample``       exact autoregressive sampling with given uniforms, site by
                  site in the order of the factorisation.
+``symmetry``     the eight symmetries of the square lattice (c4v) and the
+                 symmetrised log psi of the 2D runs.
 ``lru``          the 1D LRU ansatz (complex diagonal recurrence, GLU, residual):
                  parameter layout and log psi by the sequential recurrence.
 ``grad``         per-sample d log psi / d theta by float64 torch autograd on
@@ -29,4 +32,4 @@ each function other than itself) live in ``tests/test_oracle_pins.py`` and
 ``tests/test_oracle_lru_pins.py``.
 """
 
-from . import model, hamiltonian, sample, lru  # noqa: F401
+from . import model, hamiltonian, sample, lru, symmetry  # noqa: F401

@@ -91,7 +91,9 @@ def _torch_forward(theta_b: torch.Tensor, spins: torch.Tensor, m: M.Model) -> to
 
 
 def per_sample_grad(theta, spins, m: M.Model):
-    """(log psi [B], O [B, P]) in float64, O_s = d log psi(sigma_s) / d theta."""
+    """(log psi [B], O [B, P]) in float64, O_s = d log psi(sigma_s) / d theta (single-site inputs)."""
+    if m.patch != 1:
+        raise NotImplementedError("the autograd forward covers single-site inputs")
     spins_t = torch.as_tensor(np.asarray(spins), dtype=torch.int64)
     B = spins_t.shape[0]
     th = torch.as_tensor(np.asarray(theta, dtype=np.float64))

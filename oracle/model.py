@@ -30,8 +30,18 @@ wave function is positive and log psi = (1/2) sum_t log p_t.
 
 Parameter layout (flat float vector, row-major matrices, in this order):
 per layer  W_z[d][du], b_z[d], W_h[d][du + d], b_h[d], C[d][d], D[d][du]
-(du = 4 at l = 0, d afterwards); chain: W_z[d][2], b_z[d], W_h[d][2], b_h[d];
-then the head W_o[2][d], b_o[2].
+(du = 2 K at l = 0, d afterwards); chain: W_z[d][2], b_z[d], W_h[d][2], b_h[d];
+then the head W_o[K][d], b_o[K].  K is the size of the local alphabet: 2 for
+single-site inputs, 16 for 2x2 patches.
+
+Patches (Sec. II.F: the initial input can be a 2x2 patch of spins).  With
+``patch = 2`` the recurrence runs on the (lx/2)-by-(ly/2) grid of patches in the
+same zigzag order; patch (I, J) covers the spins (2I + a, 2J + b), a, b in {0, 1},
+and its state is k = sigma(2I, 2J) + 2 sigma(2I+1, 2J) + 4 sigma(2I, 2J+1)
++ 8 sigma(2I+1, 2J+1) (a reading: the paper gives no encoding).  u^(0) is the
+one-hot state (16 entries) of the H- and V-predecessor patches, and the head
+gives the 16-way conditional of the patch's own state, so log psi = (1/2) sum
+over patches of log p(k_t | k_<t).
 
 ``mode="seq"`` runs the plain sequential recurrence and is the authority.
 ``mode="scan"`` replaces the loop along each row by a Blelloch up-sweep /
@@ -58,10 +68,25 @@ class Model:
     ly: int
     n_layers: int
     d: int
+    patch: int = 1
 
     @property
     def n_sites(self) -> int:
         return self.lx * self.ly
+
+    @property
+    def px(self) -> int:
+        """Columns of the grid the recurrence runs on (patches)."""
+        return self.lx // self.patch
+
+    @property
+    def py(self) -> int:
+        return self.ly // self.patch
+
+    @property
+    def n_states(self) -> int:
+        """Size of the local alphabet K: 2 per site, 16 per 2x2 patch."""
+        return 2 ** (self.patch * self.patch)
 
     def __post_init__(self):
         if self.geometry not in ("chain", "snake2d"):
@@ -70,6 +95,10 @@ class Model:
             raise ValueError("the chain ansatz is one minGRU layer on ly = 1")
         if min(self.lx, self.ly, self.n_layers, self.d) < 1:
             raise ValueError("sizes must be positive")
+        if self.patch not in (1, 2):
+            raise ValueError("patch must be 1 or 2")
+        if self.patch == 2 and (self.geometry != "snake2d" or self.lx % 2 or self.ly % 2):
+            raise ValueError("2x2 patches need the 2D snake on even lattice sides")
 
 
 def snake_tensor_shapes(n_layers: int, d: int, du0: int = 4, n_out: int = 2):
@@ -101,7 +130,7 @@ def tensor_shapes(m: Model) -> list[tuple[str, tuple[int, ...]]]:
     if m.geometry == "chain":
         return [("Wz0", (d, 2)), ("bz0", (d,)), ("Wh0", (d, 2)), ("bh0", (d,)),
                 ("Wo", (2, d)), ("bo", (2,))]
-    return snake_tensor_shapes(m.n_layers, d)
+    return snake_tensor_shapes(m.n_layers, d, du0=2 * m.n_states, n_out=m.n_states)
 
 
 def n_params(m: Model) -> int:
@@ -146,14 +175,32 @@ def v_pred(i: int, j: int) -> tuple[int, int]:
     return (i, j - 1)
 
 
-def _onehot_at(spins: np.ndarray, lx: int, ly: int, i: int, j: int) -> np.ndarray:
-    """One-hot of the spin at (i, j) for every batch row; zeros outside the lattice."""
-    b = spins.shape[0]
-    out = np.zeros((b, 2))
+def _onehot_at(states: np.ndarray, lx: int, ly: int, i: int, j: int, k: int = 2) -> np.ndarray:
+    """One-hot (k entries) of the state at grid site (i, j) for every batch row; zeros outside."""
+    b = states.shape[0]
+    out = np.zeros((b, k))
     if 0 <= i < lx and 0 <= j < ly:
-        s = spins[:, j * lx + i].astype(np.int64)
+        s = states[:, j * lx + i].astype(np.int64)
         out[np.arange(b), s] = 1.0
     return out
+
+
+def patch_states(spins: np.ndarray, m: Model) -> np.ndarray:
+    """Local states on the recurrence grid, [B, px * py] (grid row-major).
+
+    patch = 1: the spins themselves.  patch = 2: patch (I, J) has state
+    sigma(2I, 2J) + 2 sigma(2I+1, 2J) + 4 sigma(2I, 2J+1) + 8 sigma(2I+1, 2J+1).
+    """
+    spins = np.asarray(spins).astype(np.int64)
+    if m.patch == 1:
+        return spins
+    B = spins.shape[0]
+    lat = spins.reshape(B, m.ly, m.lx)             # [b, y, x]
+    out = np.zeros((B, m.py, m.px), dtype=np.int64)
+    for b_ in range(2):
+        for a_ in range(2):
+            out += lat[:, b_::2, a_::2] << (a_ + 2 * b_)
+    return out.reshape(B, m.px * m.py)
 
 
 # ----------------------------------------------------------------------------
@@ -243,20 +290,22 @@ def _forward_chain(P, spins, m: Model, mode: str, keep_hidden: bool):
 
 
 def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool):
-    B, N = spins.shape
-    lx, ly, d, nl = m.lx, m.ly, m.d, m.n_layers
+    # the recurrence runs on the grid of sites (patch = 1) or of 2x2 patches
+    states = patch_states(spins, m)
+    B, N = states.shape
+    lx, ly, d, nl, K = m.px, m.py, m.d, m.n_layers, m.n_states
     frontier = [np.zeros((B, lx, d)) for _ in range(nl)]   # h^(l) of the previous row
     logp = np.empty((B, N))
     hidden = [np.zeros((B, N, d)) for _ in range(nl)] if keep_hidden else None
     for j in range(ly):
         cols = snake_row(lx, j)                              # visiting order
         # layer-0 input at every site of the row, indexed by column i
-        u = np.zeros((B, lx, 4))
+        u = np.zeros((B, lx, 2 * K))
         for i in range(lx):
             hi, hj = h_pred(i, j)
             vi, vj = v_pred(i, j)
-            u[:, i, 0:2] = _onehot_at(spins, lx, ly, hi, hj)
-            u[:, i, 2:4] = _onehot_at(spins, lx, ly, vi, vj)
+            u[:, i, 0:K] = _onehot_at(states, lx, ly, hi, hj, K)
+            u[:, i, K:2 * K] = _onehot_at(states, lx, ly, vi, vj, K)
         h_below = None                                       # h^(l-1) of this row
         for l in range(nl):
             hV = frontier[l]
@@ -277,18 +326,20 @@ def _forward_snake(P, spins, m: Model, mode: str, keep_hidden: bool):
             h_below = h
             if keep_hidden:
                 hidden[l][:, j * lx: (j + 1) * lx] = h
-        logits = u @ P["Wo"].T + P["bo"]                     # [B, lx, 2]
+        logits = u @ P["Wo"].T + P["bo"]                     # [B, lx, K]
         for i in range(lx):
-            logp[:, j * lx + i] = _site_logp(logits[:, i], spins[:, j * lx + i])
+            logp[:, j * lx + i] = _site_logp(logits[:, i], states[:, j * lx + i])
     return logp, hidden
 
 
 def forward(theta, spins, m: Model, mode: str = "seq", keep_hidden: bool = False):
-    """Per-site log p in lattice row-major order, [B, N], and optionally hidden states.
+    """Per-site log p in grid row-major order, and optionally hidden states.
 
     ``spins`` is an int array [B, N] with values in {0, 1}, row-major (site
-    y * lx + x).  Returns ``(logp, hidden)``; ``hidden[l]`` is h^(l) at every
-    site, [B, N, d], when ``keep_hidden`` is set, else ``None``.
+    y * lx + x).  Returns ``(logp, hidden)``: logp is [B, px * py], one entry per
+    site (patch = 1: [B, N] in lattice order) or per 2x2 patch (patch I + px J);
+    ``hidden[l]`` is h^(l) on the same grid, [B, px * py, d], when
+    ``keep_hidden`` is set, else ``None``.
     """
     spins = np.asarray(spins)
     if spins.ndim != 2 or spins.shape[1] != m.n_sites:

@@ -475,3 +475,141 @@ def test_f1_sampler_decision_rule():
     s, _ = S.sample(th, u, m)
     p1 = S.conditionals(th, s, m)
     assert ((u < p1) == (s == 1)).all()
+
+
+# ----------------------------------------------------------------------------
+# f2: 2x2 patch inputs (Sec. II.F) and the c4v symmetrisation of the 2D runs
+# (Sec. III.C, Tables II and VI).  The patch encoding and the c4v formula are
+# readings (the paper gives neither); these pins fix what any such reading must
+# satisfy: a bijective local alphabet, causality on the patch grid,
+# normalisation, the group structure, invariance, and E_loc = (H psi)/psi.
+# ----------------------------------------------------------------------------
+
+from oracle import symmetry as S  # noqa: E402
+
+
+def test_patch_states_are_a_bijection_of_the_four_spins():
+    """The 16 configurations of a 2x2 lattice map to the 16 states, one each; a
+    single up spin at (a, b) of the patch is state 2^(a + 2b)."""
+    m = M.Model("snake2d", 2, 2, 1, 4, patch=2)
+    cfg = M.all_configs(4)
+    st = M.patch_states(cfg, m)[:, 0]
+    assert sorted(st.tolist()) == list(range(16))
+    for a in range(2):
+        for b in range(2):
+            one = np.zeros((1, 4), dtype=np.int8)
+            one[0, b * 2 + a] = 1
+            assert M.patch_states(one, m)[0, 0] == 2 ** (a + 2 * b)
+    # patches tile the lattice: patch (I, J) reads only its own four spins
+    m2 = M.Model("snake2d", 6, 4, 1, 4, patch=2)
+    sp = np.zeros((1, 24), dtype=np.int8)
+    sp[0, 3 * 6 + 5] = 1                       # spin (5, 3): patch (2, 1), a = b = 1
+    st = M.patch_states(sp, m2)[0]
+    assert st.tolist() == [0, 0, 0, 0, 0, 8]
+
+
+@pytest.mark.parametrize("lx,ly,nl,d", [(4, 4, 3, 8), (4, 2, 2, 6), (2, 6, 3, 5), (6, 2, 2, 4)])
+def test_patch_normalisation(lx, ly, nl, d):
+    """sum over all 2^N configurations of |psi|^2 = 1 with 16-way conditionals on
+    the patch grid (three layers: the residual is active)."""
+    m = M.Model("snake2d", lx, ly, nl, d, patch=2)
+    th = _theta(m, 300 + lx + ly)
+    lp = M.logpsi(th.astype(np.float64) * 1.5, M.all_configs(lx * ly), m)
+    assert abs(math.fsum(np.exp(2.0 * lp)) - 1.0) <= 1e-12
+
+
+def test_patch_causality():
+    """Changing a spin of patch t changes log p only at patches t, t+1, ... in the
+    zigzag order of the patch grid."""
+    m = M.Model("snake2d", 6, 4, 2, 8, patch=2)
+    th = _theta(m, 77)
+    base = I.spins_bernoulli(1, 24, 78)
+    lp0, _ = M.forward(th, base, m)
+    order = [j * m.px + i for (i, j) in M.snake_order(m.px, m.py)]
+    rank = {p: r for r, p in enumerate(order)}
+    for site in range(24):
+        x, y = site % 6, site // 6
+        patch = (y // 2) * m.px + x // 2
+        s = base.copy()
+        s[0, site] ^= 1
+        lp, _ = M.forward(th, s, m)
+        changed = np.nonzero(np.abs(lp[0] - lp0[0]) > 0)[0]
+        assert all(rank[p] >= rank[patch] for p in changed)
+        assert patch in changed    # the patch's own conditional sees its own state
+
+
+def test_patch_head_only_and_zero_parameters():
+    """With every parameter zero but the head bias, each patch is drawn from
+    softmax(b_o) independently; with all zero, log psi = -(N/2) ln 2."""
+    m = M.Model("snake2d", 4, 6, 2, 8, patch=2)
+    P = M.n_params(m)
+    th = np.zeros(P)
+    s = I.spins_bernoulli(5, 24, 9)
+    assert np.allclose(M.logpsi(th, s, m), -12.0 * math.log(2.0), atol=1e-12)
+    bo = I.rng(10).standard_normal(16)
+    th[P - 16:] = bo
+    logsm = bo - np.log(np.exp(bo).sum())
+    want = 0.5 * logsm[M.patch_states(s, m)].sum(axis=1)
+    assert np.allclose(M.logpsi(th, s, m), want, atol=1e-12)
+
+
+def test_patch_parameter_counts():
+    """n_params of the patch model equals the tensor-shape count that the paper's
+    figures are checked against (about 800,000 and about 7.1 million)."""
+    for nl, d, want in ((3, 256, 816656), (6, 512, 7141392)):
+        m = M.Model("snake2d", 52, 52, nl, d, patch=2)
+        assert M.n_params(m) == want
+        shapes = M.snake_tensor_shapes(nl, d, du0=32, n_out=16)
+        assert sum(int(np.prod(s)) for _, s in shapes) == want
+
+
+def test_c4v_is_the_symmetry_group_of_the_square():
+    """Eight distinct site permutations, closed under composition, with inverses;
+    they preserve the nearest-neighbour bonds of the open lattice."""
+    for L in (2, 3, 4, 5):
+        perms = S.c4v_perms(L)
+        keys = {tuple(p) for p in perms}
+        assert len(keys) == 8
+        for p in perms:
+            assert sorted(p.tolist()) == list(range(L * L))
+            for q in perms:
+                assert tuple(p[q]) in keys          # closure
+            assert tuple(np.argsort(p)) in keys      # inverse
+        bonds = {frozenset(b) for b in H.bonds(L, L)}
+        for p in perms:
+            assert {frozenset((p[a], p[b])) for a, b in H.bonds(L, L)} == bonds
+
+
+@pytest.mark.parametrize("patch", [1, 2])
+def test_c4v_invariance_and_normalisation(patch):
+    """psi_c4v(sigma o T_k) = psi_c4v(sigma) for every configuration and k, and
+    the symmetrised wave function stays normalised (4x4, all 2^16 states)."""
+    m = M.Model("snake2d", 4, 4, 2, 8, patch=patch)
+    th = _theta(m, 400 + patch) * 1.5
+    cfg = M.all_configs(16)
+    fn = lambda c: M.logpsi(th, c, m)   # noqa: E731
+    lp = S.logpsi_c4v(fn, cfg, 4)
+    assert abs(math.fsum(np.exp(2.0 * lp)) - 1.0) <= 1e-12
+    for t in S.transformed(cfg[::97], 4):
+        assert np.allclose(S.logpsi_c4v(fn, t, 4), lp[::97], atol=1e-12)
+    # the unsymmetrised model is not invariant (so the test above is not vacuous)
+    assert np.abs(fn(S.transformed(cfg[::97], 4)[1]) - fn(cfg[::97])).max() > 1e-3
+
+
+@pytest.mark.parametrize("patch", [1, 2])
+def test_c4v_local_energy_matches_sparse_hamiltonian(patch):
+    """E_loc of the symmetrised wave function from the connected configurations
+    equals (H psi_c4v)(sigma) / psi_c4v(sigma) with H built from Pauli matrices
+    (4x4 open Heisenberg, Marshall basis), and its |psi|^2 average is >= E_0."""
+    m = M.Model("snake2d", 4, 4, 2, 8, patch=patch)
+    th = _theta(m, 500 + patch)
+    ham = H.Hamiltonian("heisenberg", 4, 4)
+    fn = lambda c: S.logpsi_c4v(lambda t: M.logpsi(th, t, m), c, 4)   # noqa: E731
+    cfg = H.all_bits(16)
+    lp_all = fn(cfg)
+    e_dense = H.local_energy_dense(lp_all, ham)
+    pick = I.rng(11).choice(len(cfg), size=40, replace=False)
+    e_conn = H.local_energy(fn, ham, cfg[pick])
+    assert np.allclose(e_conn, e_dense[pick], rtol=1e-10, atol=1e-10)
+    p = np.exp(2.0 * lp_all)
+    assert float(p @ e_dense) >= H.ground_energy(ham) - 1e-9
