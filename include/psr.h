@@ -75,15 +75,39 @@ typedef struct {
     int32_t d;          /* hidden size d = d_h; 32, 64, 128 or 256 */
     int32_t precision;  /* PSR_FP32, PSR_BF16 or PSR_FP16 (arithmetic of the dense projections) */
     int32_t ckpt_rows;  /* rows per backward checkpoint chunk; 0 = max(1, 128 / lx) */
+    int32_t patch;      /* 0 or 1: single-site inputs; 2: 2x2 patches (Sec. II.F), snake only, even lx, ly */
+    int32_t symmetry;   /* PSR_SYM_NONE or PSR_SYM_C4V (square snake lattices) */
 } psr_model_desc;
+
+/* Patches (patch = 2): the recurrence runs on the (lx/2)-by-(ly/2) grid of 2x2
+ * patches in the same zigzag order; patch (I, J) covers the spins (2I + a, 2J + b)
+ * and has the state k = s(2I,2J) + 2 s(2I+1,2J) + 4 s(2I,2J+1) + 8 s(2I+1,2J+1)
+ * of a 16-letter alphabet; u^(0) is the one-hot state of the H- and V-predecessor
+ * patches (du = 32 at layer 0) and the head is a 16-way softmax (W_o[16][d],
+ * b_o[16]).  log psi = 1/2 sum over patches of log p(k_t | k_<t); logp_site
+ * outputs are per patch, [B][(lx/2) (ly/2)] in grid row-major order.
+ *
+ * Symmetry (Sec. III.C: the 2D runs impose the c4v symmetry of the lattice):
+ * with T_0..T_7 the eight symmetries of the L-by-L lattice acting on site
+ * positions, |psi_c4v(sigma)|^2 = (1/8) sum_k |psi(sigma o T_k)|^2, i.e.
+ * log psi_c4v = 1/2 [logsumexp_k 2 log psi(sigma o T_k) - log 8] (the paper
+ * gives no formula; this form keeps normalisation and exact sampling).  The
+ * library evaluates the eight transformed configurations with the same kernels
+ * and combines them in FP64.  T_k maps (x, y) to: (x, y), (L-1-y, x),
+ * (L-1-x, L-1-y), (y, L-1-x), (L-1-x, y), (x, L-1-y), (y, x), (L-1-y, L-1-x).
+ * psr_logpsi_backward and psr_sample support neither patches nor symmetry
+ * (PSR_EUNSUPPORTED). */
+#define PSR_SYM_NONE   0
+#define PSR_SYM_C4V    1
 
 /*
  * Parameter layout (Sec. II.C for the chain, Sec. II.F-G for the snake):
  *   chain : W_z[d][2], b_z[d], W_h[d][2], b_h[d], W_o[2][d], b_o[2]
  *   snake : for each layer l = 0..n_layers-1
  *             W_z[d][du], b_z[d], W_h[d][du+d], b_h[d], C[d][d], D[d][du]
- *           with du = 4 at l = 0 (one-hot spins of the two causal
- *           predecessors) and du = d above; then W_o[2][d], b_o[2].
+ *           with du = 2K at l = 0 (one-hot states of the two causal
+ *           predecessors; K = 2 for single sites, 16 for 2x2 patches) and
+ *           du = d above; then W_o[K][d], b_o[K].
  * Matrices are row-major (output index first).  W_h multiplies [u, h_V].
  */
 int64_t psr_param_count(const psr_model_desc* m);  /* P, or a negative code */

@@ -21,11 +21,12 @@ __all__ = [
     "param_count", "param_offsets", "max_connected", "workspace_bytes",
     "logpsi", "logpsi_static", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
     "LogPsi", "per_sample_grad", "timing_begin", "timing_end",
-    "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "FP16", "TFIM", "HEISENBERG",
+    "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "FP16", "SYM_NONE", "SYM_C4V", "TFIM", "HEISENBERG",
 ]
 
 CHAIN_1D, SNAKE_2D = 0, 1
 FP32, BF16, FP16 = 0, 1, 2
+SYM_NONE, SYM_C4V = 0, 1
 TFIM, HEISENBERG = 0, 1
 OP_LOGPSI, OP_LOCAL_ENERGY, OP_BACKWARD, OP_SAMPLE = 0, 1, 2, 3
 
@@ -42,7 +43,7 @@ class PsrError(RuntimeError):
 class _ModelDesc(ctypes.Structure):
     _fields_ = [("geometry", ctypes.c_int32), ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("d", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("ckpt_rows", ctypes.c_int32)]
+                ("ckpt_rows", ctypes.c_int32), ("patch", ctypes.c_int32), ("symmetry", ctypes.c_int32)]
 
 
 class _HamDesc(ctypes.Structure):
@@ -60,13 +61,21 @@ class Model:
     d: int
     precision: int = FP32
     ckpt_rows: int = 0
+    patch: int = 1          # 2: 2x2 patch inputs (16-letter alphabet, 16-way head)
+    symmetry: int = 0       # SYM_C4V: c4v-symmetrised log psi (square lattices)
 
     def c(self) -> _ModelDesc:
-        return _ModelDesc(self.geometry, self.lx, self.ly, self.n_layers, self.d, self.precision, self.ckpt_rows)
+        return _ModelDesc(self.geometry, self.lx, self.ly, self.n_layers, self.d, self.precision, self.ckpt_rows,
+                          self.patch, self.symmetry)
 
     @property
     def n_sites(self) -> int:
         return self.lx * self.ly
+
+    @property
+    def n_grid(self) -> int:
+        """Sites of the grid the recurrence runs on (2x2 patches: a quarter of the spins)."""
+        return (self.lx // self.patch) * (self.ly // self.patch)
 
 
 @dataclass(frozen=True)
@@ -220,7 +229,7 @@ def logpsi(m: Model, theta: torch.Tensor, spins: torch.Tensor, site_logp: bool =
     spins = _dev(spins, torch.int8, "spins")
     B = spins.shape[0]
     out = torch.empty(B, dtype=torch.float32, device=spins.device)
-    lps = torch.empty(B, m.n_sites, dtype=torch.float32, device=spins.device) if site_logp else None
+    lps = torch.empty(B, m.n_grid, dtype=torch.float32, device=spins.device) if site_logp else None
     if ws is None:
         ws = _workspace(m, OP_LOGPSI, B, spins.device)
     _check(lib().psr_logpsi(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps), _ptr(ws),
@@ -235,7 +244,7 @@ def logpsi_static(m: Model, theta: torch.Tensor, spins: torch.Tensor, site_logp:
     spins = _dev(spins, torch.int8, "spins")
     B = spins.shape[0]
     out = torch.empty(B, dtype=torch.float32, device=spins.device)
-    lps = torch.empty(B, m.n_sites, dtype=torch.float32, device=spins.device) if site_logp else None
+    lps = torch.empty(B, m.n_grid, dtype=torch.float32, device=spins.device) if site_logp else None
     _check(lib().psr_logpsi_static(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(lps),
                                    _stream(spins.device)))
     return (out, lps) if site_logp else out

@@ -53,13 +53,25 @@ static int check_model(const psr_model_desc* m, Geom* out) {
     if (m->precision != PSR_FP32 && m->precision != PSR_BF16 && m->precision != PSR_FP16)
         return fail(PSR_EINVAL, "precision %d is not PSR_FP32, PSR_BF16 or PSR_FP16", m->precision);
     if (m->ckpt_rows < 0) return fail(PSR_EINVAL, "ckpt_rows must be >= 0");
+    const int patch = m->patch == 0 ? 1 : m->patch;
+    if (patch != 1 && patch != 2) return fail(PSR_EINVAL, "patch %d is not 1 or 2", m->patch);
+    if (patch == 2 && (m->geometry != PSR_SNAKE_2D || m->lx % 2 || m->ly % 2))
+        return fail(PSR_EINVAL, "2x2 patches need the 2D snake on even lattice sides (got %d x %d)", m->lx, m->ly);
+    if (m->symmetry != PSR_SYM_NONE && m->symmetry != PSR_SYM_C4V)
+        return fail(PSR_EINVAL, "symmetry %d is not PSR_SYM_NONE or PSR_SYM_C4V", m->symmetry);
+    if (m->symmetry == PSR_SYM_C4V && (m->geometry != PSR_SNAKE_2D || m->lx != m->ly))
+        return fail(PSR_EINVAL, "c4v symmetry needs a square 2D lattice (got %d x %d)", m->lx, m->ly);
     Geom g;
     g.chain = (m->geometry == PSR_CHAIN_1D);
-    g.lx = m->lx;
-    g.ly = m->ly;
+    g.patch = patch;
+    g.slx = m->lx;
+    g.sly = m->ly;
+    g.lx = m->lx / patch;
+    g.ly = m->ly / patch;
     g.nl = m->n_layers;
     g.d = m->d;
     g.prec = m->precision == PSR_BF16 ? kBF16 : (m->precision == PSR_FP16 ? kFP16 : kFP32);
+    g.sym = m->symmetry == PSR_SYM_C4V ? 1 : 0;
     const FwdShape sh = fwd_shape(g);
     if (sh.seqs < 1)
         return fail(PSR_EUNSUPPORTED, "row length %d exceeds the %d columns of a workgroup at d = %d", g.lx, sh.cols,
@@ -90,7 +102,7 @@ void param_offsets(const Geom& g, int64_t* off, int32_t* n) {
         add(d);       // b_h
     } else {
         for (int l = 0; l < g.nl; ++l) {
-            const int64_t du = (l == 0) ? 4 : d;
+            const int64_t du = (l == 0) ? 2 * n_states(g) : d;
             add(d * du);          // W_z
             add(d);               // b_z
             add(d * (du + d));    // W_h
@@ -99,8 +111,8 @@ void param_offsets(const Geom& g, int64_t* off, int32_t* n) {
             add(d * du);          // D
         }
     }
-    add(2 * d);   // W_o
-    add(2);       // b_o
+    add(n_states(g) * d);   // W_o
+    add(n_states(g));       // b_o
     off[k] = p;
     *n = k;
 }
@@ -130,9 +142,10 @@ Prepared prepared_layout(const Geom& g) {
     }
     pl.frag_bytes = fb > 0 ? fb : 256;
     int64_t t = 0;
-    pl.t0z = t; t += 9 * d;
-    pl.t0h = t; t += 9 * d;
-    pl.t0d = t; t += 9 * d;
+    const int64_t nst = (int64_t)(n_states(g) + 1) * (n_states(g) + 1);   // (H-pred, V-pred) states, 'outside' included
+    pl.t0z = t; t += nst * d;
+    pl.t0h = t; t += nst * d;
+    pl.t0d = t; t += nst * d;
     for (int l = 0; l < 8; ++l) {
         pl.bias_z[l] = 0;
         pl.bias_h[l] = 0;
@@ -141,8 +154,9 @@ Prepared prepared_layout(const Geom& g) {
         pl.bias_z[l] = t; t += d;
         pl.bias_h[l] = t; t += d;
     }
-    pl.head_w = t; t += d;
-    pl.head_b = t; t += 4;
+    // two classes: the logit difference only; 16 classes: every row of the head
+    pl.head_w = t; t += (n_states(g) == 2 ? 1 : n_states(g)) * d;
+    pl.head_b = t; t += n_states(g) == 2 ? 4 : n_states(g);
     pl.table_floats = t;
     return pl;
 }
@@ -183,13 +197,14 @@ struct LogpsiWs {
     void* frontier;
     float* hi;
     float* lo;
+    float *hi8, *lo8;   // c4v: log psi of the eight transformed batches, [8][B]
     int64_t chunk;
 };
 
 static int64_t carve_logpsi(const Geom& g, int64_t B, void* ws, LogpsiWs* w) {
     Carver c(ws);
     const Prepared pl = prepared_layout(g);
-    const int words = (g.lx * g.ly + 31) / 32;
+    const int words = (g.slx * g.sly + 31) / 32;
     w->chunk = logpsi_chunk(g, B);
     w->packed = c.take<uint32_t>(B * words);
     w->frag = c.take<uint8_t>(pl.frag_bytes);
@@ -197,6 +212,8 @@ static int64_t carve_logpsi(const Geom& g, int64_t B, void* ws, LogpsiWs* w) {
     w->frontier = c.take<uint8_t>(w->chunk * frontier_seq_bytes(g));
     w->hi = c.take<float>(B);
     w->lo = c.take<float>(B);
+    w->hi8 = g.sym ? c.take<float>(8 * B) : nullptr;
+    w->lo8 = g.sym ? c.take<float>(8 * B) : nullptr;
     return c.used;
 }
 
@@ -211,12 +228,13 @@ struct ElocWs {
     uint32_t* desc;
     float* mel;
     float *chi, *clo, *shi, *slo;
+    float *chi8, *clo8, *shi8, *slo8;   // c4v: the eight transformed evaluations, [8][M] and [8][B]
 };
 
 static int64_t carve_eloc(const Geom& g, int64_t B, int64_t max_conn, int64_t chunk, void* ws, ElocWs* w) {
     Carver c(ws);
     const Prepared pl = prepared_layout(g);
-    const int words = (g.lx * g.ly + 31) / 32;
+    const int words = (g.slx * g.sly + 31) / 32;
     const int64_t M = B * max_conn;
     w->packed = c.take<uint32_t>(B * words);
     w->frag = c.take<uint8_t>(pl.frag_bytes);
@@ -231,6 +249,10 @@ static int64_t carve_eloc(const Geom& g, int64_t B, int64_t max_conn, int64_t ch
     w->clo = c.take<float>(M);
     w->shi = c.take<float>(B);
     w->slo = c.take<float>(B);
+    w->chi8 = g.sym ? c.take<float>(8 * M) : nullptr;
+    w->clo8 = g.sym ? c.take<float>(8 * M) : nullptr;
+    w->shi8 = g.sym ? c.take<float>(8 * B) : nullptr;
+    w->slo8 = g.sym ? c.take<float>(8 * B) : nullptr;
     return c.used;
 }
 
@@ -243,7 +265,7 @@ struct BwdWs {
 static int64_t carve_bwd(const Geom& g, int ckpt_rows, int64_t B, bool need_O, void* ws, BwdWs* w) {
     Carver c(ws);
     const BwdLayout bl = bwd_layout(g, ckpt_rows);
-    const int words = (g.lx * g.ly + 31) / 32;
+    const int words = (g.slx * g.sly + 31) / 32;
     w->packed = c.take<uint32_t>(B * words);
     w->scratch = c.take<float>(B * bl.ws_per_sample_floats);
     w->O = need_O ? c.take<float>(B * param_count(g)) : nullptr;
@@ -299,11 +321,11 @@ static void timing_before(hipStream_t st, hipEvent_t* stop) {
 
 static int run_forward(const Geom& g, const Prepared& pl, const uint32_t* packed, const uint32_t* desc,
                        int64_t q_begin, int64_t q_count, const int64_t* q_total, const uint8_t* frag, const float* tab,
-                       void* frontier, float* hi, float* lo, float* logp_site, hipStream_t st) {
+                       void* frontier, float* hi, float* lo, float* logp_site, hipStream_t st, int xform = 0) {
     FwdArgs a;
     a.g = g;
     a.spins = packed;
-    a.words_per_seq = (g.lx * g.ly + 31) / 32;
+    a.words_per_seq = (g.slx * g.sly + 31) / 32;
     a.desc = desc;
     a.q_begin = q_begin;
     a.q_count = q_count;
@@ -316,6 +338,7 @@ static int run_forward(const Geom& g, const Prepared& pl, const uint32_t* packed
     a.out_hi = hi;
     a.out_lo = lo;
     a.logp_site = logp_site;
+    a.xform = xform;
     hipEvent_t stop;
     timing_before(st, &stop);
     const int e = launch_forward(a, st);
@@ -430,12 +453,12 @@ int64_t psr_workspace_bytes(const psr_model_desc* m, int32_t op, int64_t batch, 
         psr_hamiltonian H;
         std::memset(&H, 0, sizeof(H));
         H.kind = PSR_HEISENBERG;
-        H.lx = g.lx;
-        H.ly = g.ly;
+        H.lx = g.slx;
+        H.ly = g.sly;
         Ham h;
         check_ham(&H, &h);
         int64_t mc = ham_max_connected(h);
-        if ((int64_t)g.lx * g.ly > mc) mc = (int64_t)g.lx * g.ly;   // enough for either Hamiltonian
+        if ((int64_t)g.slx * g.sly > mc) mc = (int64_t)g.slx * g.sly;   // enough for either Hamiltonian
         ElocWs w;
         const int64_t ch = chunk_seqs > 0 ? chunk_seqs : 32768;
         return carve_eloc(g, batch, mc, ch, nullptr, &w);
@@ -458,6 +481,7 @@ int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins,
     if (B < 0) return fail(PSR_EINVAL, "negative batch");
     if (B == 0) return ok();
     if (!theta || !spins || !logpsi) return fail(PSR_EINVAL, "theta, spins and logpsi must not be NULL");
+    if (g.sym && logp_site) return fail(PSR_EINVAL, "per-site log p is not defined for a symmetrised wave function");
     LogpsiWs w;
     const int64_t need = carve_logpsi(g, B, nullptr, &w);
     if (!ws || (int64_t)ws_bytes < need)
@@ -465,16 +489,23 @@ int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins,
     carve_logpsi(g, B, ws, &w);
     hipStream_t st = as_stream(stream);
     const Prepared pl = prepared_layout(g);
-    const int N = g.lx * g.ly;
+    const int N = g.slx * g.sly;   // spins per sample
     if ((r = dev_check(launch_pack_spins(spins, B, N, w.packed, st), "pack"))) return r;
     if ((r = dev_check(launch_prepare(g, pl, theta, w.frag, w.tab, st), "prepare"))) return r;
-    for (int64_t q0 = 0; q0 < B; q0 += w.chunk) {
-        const int64_t n = (B - q0 < w.chunk) ? B - q0 : w.chunk;
-        if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, w.hi,
-                                       w.lo, logp_site, st),
-                           "forward")))
-            return r;
+    // c4v: the batch read as sigma o T_k for k = 0..7, combined below
+    const int nx = g.sym ? 8 : 1;
+    for (int k = 0; k < nx; ++k) {
+        float* hi = g.sym ? w.hi8 + (size_t)k * B : w.hi;
+        float* lo = g.sym ? w.lo8 + (size_t)k * B : w.lo;
+        for (int64_t q0 = 0; q0 < B; q0 += w.chunk) {
+            const int64_t n = (B - q0 < w.chunk) ? B - q0 : w.chunk;
+            if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, hi, lo,
+                                           logp_site, st, k),
+                               "forward")))
+                return r;
+        }
     }
+    if (g.sym && (r = dev_check(launch_c4v_combine(w.hi8, w.lo8, B, w.hi, w.lo, st), "c4v combine"))) return r;
     if ((r = dev_check(launch_combine_logpsi(w.hi, w.lo, B, logpsi, st), "combine"))) return r;
     return ok();
 }
@@ -535,8 +566,8 @@ int psr_local_energy(const psr_model_desc* m, const float* theta, const psr_hami
     if (r) return r;
     Ham h;
     if ((r = check_ham(H, &h))) return r;
-    if (h.lx != g.lx || h.ly != g.ly)
-        return fail(PSR_EINVAL, "Hamiltonian lattice %d x %d differs from the model's %d x %d", h.lx, h.ly, g.lx, g.ly);
+    if (h.lx != g.slx || h.ly != g.sly)
+        return fail(PSR_EINVAL, "Hamiltonian lattice %d x %d differs from the model's %d x %d", h.lx, h.ly, g.slx, g.sly);
     if (B < 0 || chunk_seqs < 0) return fail(PSR_EINVAL, "negative batch or chunk");
     if (B == 0) return ok();
     if (!theta || !spins || !eloc || !stats) return fail(PSR_EINVAL, "theta, spins, eloc and stats must not be NULL");
@@ -549,28 +580,41 @@ int psr_local_energy(const psr_model_desc* m, const float* theta, const psr_hami
     carve_eloc(g, B, max_conn, chunk, ws, &w);
     hipStream_t st = as_stream(stream);
     const Prepared pl = prepared_layout(g);
-    const int N = g.lx * g.ly;
+    const int N = g.slx * g.sly;   // spins per sample
     if ((r = dev_check(launch_pack_spins(spins, B, N, w.packed, st), "pack"))) return r;
     if ((r = dev_check(launch_prepare(g, pl, theta, w.frag, w.tab, st), "prepare"))) return r;
     if ((r = dev_check(launch_conn_count(h, spins, B, w.n_conn, w.diag, st), "connected count"))) return r;
     if ((r = dev_check(launch_scan_counts(w.n_conn, B, w.offs, st), "scan"))) return r;
     if ((r = dev_check(launch_conn_write(h, spins, B, w.offs, 0, w.desc, w.mel, st), "connected write"))) return r;
-    // the samples themselves
-    for (int64_t q0 = 0; q0 < B; q0 += chunk) {
-        const int64_t n = (B - q0 < chunk) ? B - q0 : chunk;
-        if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, w.shi,
-                                       w.slo, nullptr, st),
-                           "forward (samples)")))
-            return r;
-    }
-    // the connected configurations, streamed in chunks; launches past the
-    // device-side total exit at once
+    // c4v: every configuration is read as sigma o T_k for k = 0..7 and combined below
+    const int nx = g.sym ? 8 : 1;
     const int64_t M = B * max_conn;
-    for (int64_t q0 = 0; q0 < M; q0 += chunk) {
-        const int64_t n = (M - q0 < chunk) ? M - q0 : chunk;
-        if ((r = dev_check(run_forward(g, pl, w.packed, w.desc, q0, n, w.offs + B, w.frag, w.tab, w.frontier, w.chi,
-                                       w.clo, nullptr, st),
-                           "forward (connected)")))
+    for (int k = 0; k < nx; ++k) {
+        float* shi = g.sym ? w.shi8 + (size_t)k * B : w.shi;
+        float* slo = g.sym ? w.slo8 + (size_t)k * B : w.slo;
+        float* chi = g.sym ? w.chi8 + (size_t)k * M : w.chi;
+        float* clo = g.sym ? w.clo8 + (size_t)k * M : w.clo;
+        // the samples themselves
+        for (int64_t q0 = 0; q0 < B; q0 += chunk) {
+            const int64_t n = (B - q0 < chunk) ? B - q0 : chunk;
+            if ((r = dev_check(run_forward(g, pl, w.packed, nullptr, q0, n, nullptr, w.frag, w.tab, w.frontier, shi,
+                                           slo, nullptr, st, k),
+                               "forward (samples)")))
+                return r;
+        }
+        // the connected configurations, streamed in chunks; launches past the
+        // device-side total exit at once
+        for (int64_t q0 = 0; q0 < M; q0 += chunk) {
+            const int64_t n = (M - q0 < chunk) ? M - q0 : chunk;
+            if ((r = dev_check(run_forward(g, pl, w.packed, w.desc, q0, n, w.offs + B, w.frag, w.tab, w.frontier, chi,
+                                           clo, nullptr, st, k),
+                               "forward (connected)")))
+                return r;
+        }
+    }
+    if (g.sym) {
+        if ((r = dev_check(launch_c4v_combine(w.shi8, w.slo8, B, w.shi, w.slo, st), "c4v combine (samples)"))) return r;
+        if ((r = dev_check(launch_c4v_combine(w.chi8, w.clo8, M, w.chi, w.clo, st), "c4v combine (connected)")))
             return r;
     }
     if ((r = dev_check(launch_eloc_combine(B, w.offs, w.diag, w.mel, w.chi, w.clo, w.shi, w.slo, eloc, st), "E_loc")))
@@ -589,6 +633,8 @@ int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_
     if (B == 0) return ok();
     if (!theta || !spins) return fail(PSR_EINVAL, "theta and spins must not be NULL");
     if ((w == nullptr) != (gout == nullptr)) return fail(PSR_EINVAL, "w and g must be both set or both NULL");
+    if (g.patch != 1 || g.sym)
+        return fail(PSR_EUNSUPPORTED, "the backward covers single-site inputs without symmetrisation");
     if (!O && !gout) return fail(PSR_EINVAL, "nothing to compute: O and g are both NULL");
     BwdWs bw;
     const int64_t need = carve_bwd(g, m->ckpt_rows, B, O == nullptr, nullptr, &bw);
@@ -596,7 +642,7 @@ int psr_logpsi_backward(const psr_model_desc* m, const float* theta, const int8_
         return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
     carve_bwd(g, m->ckpt_rows, B, O == nullptr, ws, &bw);
     hipStream_t st = as_stream(stream);
-    const int N = g.lx * g.ly;
+    const int N = g.slx * g.sly;   // spins per sample
     const int words = (N + 31) / 32;
     float* Ouse = O ? O : bw.O;
     const BwdLayout bl = bwd_layout(g, m->ckpt_rows);
@@ -616,6 +662,8 @@ int psr_sample(const psr_model_desc* m, const float* theta, const float* uniform
     if (B < 0) return fail(PSR_EINVAL, "negative batch");
     if (B == 0) return ok();
     if (!theta || !uniforms || !spins || !logpsi) return fail(PSR_EINVAL, "theta, uniforms, spins and logpsi must not be NULL");
+    if (g.patch != 1 || g.sym)
+        return fail(PSR_EUNSUPPORTED, "the sampler covers single-site inputs without symmetrisation");
     const int64_t need = sample_groups(B) * sample_ws_per_wg_floats(g) * (int64_t)sizeof(float);
     if (!ws || (int64_t)ws_bytes < need)
         return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);

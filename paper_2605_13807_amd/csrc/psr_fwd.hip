@@ -88,10 +88,11 @@ __global__ void prep_frag_f32(const float* __restrict__ theta, MatSrc src, int d
     out[e] = theta[src.base + (int64_t)r * src.ld + src.coff + k];
 }
 
-// Layer-0 gathers.  state = 3*sH + sV with s = spin value or 2 (outside).
-// snake: u^(0) = [onehot(sH), onehot(sV)];  chain: u^(0) = onehot(sH).
+// Layer-0 gathers.  state = (K+1) sH + sV with s = the local state (a spin, or a
+// 2x2 patch's 16-letter state) or K (outside the lattice).
+// snake: u^(0) = [onehot_K(sH), onehot_K(sV)];  chain: u^(0) = onehot_2(sH).
 struct Tab0Src {
-    int chain, d;
+    int chain, d, K;
     int64_t wz, bz, wh, bh, dd;   // theta offsets of W_z^(0), b_z^(0), W_h^(0), b_h^(0), D^(0) (dd < 0: none)
     int ldz, ldh;                 // row strides of W_z^(0) and W_h^(0)
 };
@@ -99,19 +100,20 @@ struct Tab0Src {
 __global__ void prep_tab0(const float* __restrict__ theta, Tab0Src s, float* __restrict__ tz, float* __restrict__ th,
                           float* __restrict__ td) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 9 * s.d) return;
+    const int K = s.K;
+    if (e >= (K + 1) * (K + 1) * s.d) return;
     const int st = e / s.d, u = e % s.d;
-    const int sH = st / 3, sV = st % 3;
+    const int sH = st / (K + 1), sV = st % (K + 1);
     float z = theta[s.bz + u], h = theta[s.bh + u], dv = 0.0f;
-    if (sH < 2) {
+    if (sH < K) {
         z += theta[s.wz + (int64_t)u * s.ldz + sH];
         h += theta[s.wh + (int64_t)u * s.ldh + sH];
-        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * 4 + sH];
+        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * (2 * K) + sH];
     }
-    if (!s.chain && sV < 2) {
-        z += theta[s.wz + (int64_t)u * s.ldz + 2 + sV];
-        h += theta[s.wh + (int64_t)u * s.ldh + 2 + sV];
-        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * 4 + 2 + sV];
+    if (!s.chain && sV < K) {
+        z += theta[s.wz + (int64_t)u * s.ldz + K + sV];
+        h += theta[s.wh + (int64_t)u * s.ldh + K + sV];
+        if (s.dd >= 0) dv += theta[s.dd + (int64_t)u * (2 * K) + K + sV];
     }
     const int p = st * s.d + unit_pos(u, s.d);
     tz[p] = z;
@@ -126,6 +128,16 @@ __global__ void prep_head(const float* __restrict__ theta, int64_t src_w, int64_
     if (u >= d) return;
     w[unit_pos(u, d)] = theta[src_w + u] - theta[src_w + d + u];
     if (u == 0) b[0] = theta[src_b] - theta[src_b + 1];
+}
+
+// Head of the K-class log-softmax (2x2 patches, K = 16): every row of W_o in slot order, and b_o.
+__global__ void prep_head_k(const float* __restrict__ theta, int64_t src_w, int64_t src_b, int d, int K,
+                            float* __restrict__ w, float* __restrict__ b) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K * d) return;
+    const int cls = e / d, u = e % d;
+    w[cls * d + unit_pos(u, d)] = theta[src_w + e];
+    if (u == 0) b[cls] = theta[src_b + cls];
 }
 
 __global__ void prep_vec(const float* __restrict__ theta, int64_t src, int d, int rows, float* __restrict__ out) {
@@ -148,7 +160,7 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
             const int64_t fo = pl.frag[l][m];
             // tensor order per layer: W_z, b_z, W_h, b_h, C, D
             const int64_t wz = off[6 * l + 0], wh = off[6 * l + 2], cc = off[6 * l + 4], dd = off[6 * l + 5];
-            const int du = (l == 0) ? 4 : d;
+            const int du = (l == 0) ? 2 * n_states(g) : d;
             MatSrc s;
             switch (m) {
                 case 0: s = MatSrc{wz, du, 0}; break;
@@ -171,6 +183,7 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
     Tab0Src s0;
     s0.chain = g.chain;
     s0.d = d;
+    s0.K = n_states(g);
     s0.wz = off[0];
     s0.bz = off[1];
     s0.wh = off[2];
@@ -181,16 +194,21 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
         s0.ldh = 2;
     } else {
         s0.dd = off[5];
-        s0.ldz = 4;
-        s0.ldh = 4 + d;
+        s0.ldz = 2 * s0.K;
+        s0.ldh = 2 * s0.K + d;
     }
-    prep_tab0<<<(9 * d + T - 1) / T, T, 0, st>>>(theta, s0, tab + pl.t0z, tab + pl.t0h, tab + pl.t0d);
+    const int nst = (s0.K + 1) * (s0.K + 1);
+    prep_tab0<<<(nst * d + T - 1) / T, T, 0, st>>>(theta, s0, tab + pl.t0z, tab + pl.t0h, tab + pl.t0d);
     for (int l = 1; l < g.nl; ++l) {
         prep_vec<<<(d + T - 1) / T, T, 0, st>>>(theta, off[6 * l + 1], d, 1, tab + pl.bias_z[l]);
         prep_vec<<<(d + T - 1) / T, T, 0, st>>>(theta, off[6 * l + 3], d, 1, tab + pl.bias_h[l]);
     }
     const int ih = g.chain ? 4 : 6 * g.nl;   // index of W_o in the tensor list
-    prep_head<<<(d + T - 1) / T, T, 0, st>>>(theta, off[ih], off[ih + 1], d, tab + pl.head_w, tab + pl.head_b);
+    if (n_states(g) == 2)
+        prep_head<<<(d + T - 1) / T, T, 0, st>>>(theta, off[ih], off[ih + 1], d, tab + pl.head_w, tab + pl.head_b);
+    else
+        prep_head_k<<<(n_states(g) * d + T - 1) / T, T, 0, st>>>(theta, off[ih], off[ih + 1], d, n_states(g),
+                                                                 tab + pl.head_w, tab + pl.head_b);
     return (int)hipGetLastError();
 }
 
@@ -212,7 +230,9 @@ int launch_prepare(const Geom& g, const Prepared& pl, const float* theta, uint8_
 // also keeps sequences that share a chunk or a DPP row independent.
 
 
-template <int P, int D, int NTC, bool CROSS, bool CHAIN, bool ALIGNED, bool LDSF>
+// PATCH: 2x2 patch inputs (a 16-letter alphabet per grid site, a 16-way head).
+// XF: the spins are read through a c4v symmetry of the lattice (a.xform).
+template <int P, int D, int NTC, bool CROSS, bool CHAIN, bool ALIGNED, bool LDSF, bool PATCH = false, bool XF = false>
 __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
     using F = MF<P>;
     typedef typename F::Frag Frag;
@@ -269,12 +289,25 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
             flip[c] = (int)(fa | ((fb == fa ? 0xFFFFu : fb) << 16));
         }
     }
+    // spin at lattice site s of the configuration (XF: read as sigma o T_xform, a c4v symmetry)
     auto spin = [&](int c, int site) -> int {
+        if constexpr (XF) site = xform_site(site, a.xform, G.slx);
         const uint32_t* w = a.spins + (size_t)srow[c] * a.words_per_seq;
         const int v = (int)((w[site >> 5] >> (site & 31)) & 1u);
         const int fa = flip[c] & 0xFFFF, fb = (int)((uint32_t)flip[c] >> 16);
         return v ^ (int)(site == fa) ^ (int)(site == fb);
     };
+    // local state at grid site (i, jj): the spin, or the 16-letter state of the 2x2 patch
+    // s(2i, 2jj) + 2 s(2i+1, 2jj) + 4 s(2i, 2jj+1) + 8 s(2i+1, 2jj+1)
+    auto local_state = [&](int c, int i, int jj) -> int {
+        if constexpr (PATCH) {
+            const int s0 = (2 * jj) * G.slx + 2 * i;
+            return spin(c, s0) | (spin(c, s0 + 1) << 1) | (spin(c, s0 + G.slx) << 2) | (spin(c, s0 + G.slx + 1) << 3);
+        } else {
+            return spin(c, jj * lx + i);
+        }
+    };
+    constexpr int K = PATCH ? 16 : 2;   // local alphabet; K also marks 'outside the lattice'
     auto seq_local = [&](int c) -> int64_t { return valid[c] ? (q0 + kq[c] - a.q_begin) : 0; };
     float keep[NTC];   // 0 at a row start: h_H is zero outside the lattice
 #pragma unroll
@@ -297,15 +330,15 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
         for (int c = 0; c < NTC; ++c) {
             const int i = (j & 1) ? (lx - 1 - t[c]) : t[c];
             iph[c] = i;
-            int sH = 2, sV = 2;
+            int sH = K, sV = K;
             const int ih = (j & 1) ? i + 1 : i - 1;
             own[c] = 0;
             if (valid[c]) {
-                if (ih >= 0 && ih < lx) sH = spin(c, j * lx + ih);
-                if (j > 0) sV = spin(c, (j - 1) * lx + i);
-                own[c] = spin(c, j * lx + i);
+                if (ih >= 0 && ih < lx) sH = local_state(c, ih, j);
+                if (j > 0) sV = local_state(c, i, j - 1);
+                own[c] = local_state(c, i, j);
             }
-            st[c] = 3 * sH + sV;
+            st[c] = (K + 1) * sH + sV;
         }
         const bool vert = (!CHAIN) && (j > 0);
         // this row's frontier columns (layer l adds l * fl_stride bytes)
@@ -322,6 +355,12 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
         float l0[NTC];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) l0[c] = 0.0f;
+        // PATCH: all 16 logits (partial over this lane's units)
+        float lk[PATCH ? 16 : 1][NTC];
+#pragma unroll
+        for (int k = 0; k < (PATCH ? 16 : 1); ++k)
+#pragma unroll
+            for (int c = 0; c < NTC; ++c) lk[k][c] = 0.0f;
 
         // h_V operand of the layer being computed: the previous row's frontier (0 on row 0).
         // Layer 0's is loaded here; layer l+1's is loaded while layer l forms its output.
@@ -615,6 +654,19 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
                             set_pair<P, D>(xn[c], 4 * mt + 2, gelu_tail(ao[sl][c][2]), gelu_tail(ao[sl][c][3]));
                             pin_tile<P, D>(xn[c], mt);
                         }
+                    } else if constexpr (PATCH) {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c) {
+                            float x[4];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) x[i] = gelu_tail(ao[sl][c][i]);
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) {
+                                const f32x4 hw = ld16(tab + a.pl.head_w + k * D + 4 * mt, goff);
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) lk[k][c] = fmaf(hw[i], x[i], lk[k][c]);
+                            }
+                        }
                     } else {
                         const f32x4 hw0 = ld16(tab + a.pl.head_w + 4 * mt, goff);
 #pragma unroll
@@ -693,16 +745,35 @@ __global__ void __launch_bounds__(kWaves * 64) fwd_kernel(const FwdArgs a) {
         const float bod = tab[a.pl.head_b];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
-            float v = l0[c];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            v += bod;
-            // dl = (logit of the other spin) - (logit of the own spin)
-            const float dl = own[c] ? v : -v;
-            // log p = -softplus(dl) = -(max(dl, 0) + ln(1 + e^-|dl|)), in base 2 on the
-            // hardware exp2/log2 (1 + e rounds to 1 only where e < 2^-24)
-            const float e = __builtin_amdgcn_exp2f(fabsf(dl) * kNegLog2e);
-            const float lp = -(fmaxf(dl, 0.0f) + kLn2 * __builtin_amdgcn_logf(1.0f + e));
+            float lp;
+            if constexpr (PATCH) {
+                // log p(k_own) = l_own - max - ln sum_k exp(l_k - max) over the 16 logits
+                float v[16], mx = -3.0e38f, vo = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    float t2 = lk[k][c];
+                    t2 += __shfl_xor(t2, 16);
+                    t2 += __shfl_xor(t2, 32);
+                    v[k] = t2 + tab[a.pl.head_b + k];
+                    mx = fmaxf(mx, v[k]);
+                    vo = (k == own[c]) ? v[k] : vo;
+                }
+                float se = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) se += __builtin_amdgcn_exp2f((v[k] - mx) * -kNegLog2e);
+                lp = (vo - mx) - kLn2 * __builtin_amdgcn_logf(se);
+            } else {
+                float v = l0[c];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                v += bod;
+                // dl = (logit of the other spin) - (logit of the own spin)
+                const float dl = own[c] ? v : -v;
+                // log p = -softplus(dl) = -(max(dl, 0) + ln(1 + e^-|dl|)), in base 2 on the
+                // hardware exp2/log2 (1 + e rounds to 1 only where e < 2^-24)
+                const float e = __builtin_amdgcn_exp2f(fabsf(dl) * kNegLog2e);
+                lp = -(fmaxf(dl, 0.0f) + kLn2 * __builtin_amdgcn_logf(1.0f + e));
+            }
             if (valid[c]) {
                 neumaier(ls[c], lc[c], lp);
                 if (a.logp_site && g == 0) a.logp_site[(size_t)(q0 + kq[c]) * N + j * lx + iph[c]] = lp;
@@ -768,7 +839,9 @@ FwdShape fwd_shape(const Geom& g) {
     }
     // split frontier rows: d values of 4 bytes (high and low parts) plus 16 bytes of padding
     const int64_t pitch = (int64_t)g.d * 4 + 16;
-    s.lds_frontier = (!g.chain && g.prec != kFP32 &&
+    // the patch and symmetry kernels are instantiated for the general layout only
+    if (g.patch == 2 || g.sym) s.cross_wave = 1;
+    s.lds_frontier = (!g.chain && g.prec != kFP32 && g.patch == 1 && !g.sym &&
                       (int64_t)g.d * 4 + (int64_t)s.seqs * g.nl * g.lx * pitch <= kLdsFrontier) ? 1 : 0;
     return s;
 }
@@ -778,7 +851,16 @@ static int launch_t(const FwdArgs& a, hipStream_t st) {
     const int64_t blocks = (a.q_count + a.sh.seqs - 1) / a.sh.seqs;
     if (blocks <= 0) return 0;
     const dim3 grid((unsigned)blocks), block(kWaves * 64);
-    if (a.g.chain) {
+    if (a.g.patch == 2 || a.g.sym) {
+        // 2x2 patches and c4v-symmetrised evaluations: the general layout (rows may straddle
+        // waves, frontier in global memory)
+        if (a.g.patch == 2 && a.g.sym)
+            fwd_kernel<P, D, NTC, true, false, false, false, true, true><<<grid, block, 0, st>>>(a);
+        else if (a.g.patch == 2)
+            fwd_kernel<P, D, NTC, true, false, false, false, true, false><<<grid, block, 0, st>>>(a);
+        else
+            fwd_kernel<P, D, NTC, true, false, false, false, false, true><<<grid, block, 0, st>>>(a);
+    } else if (a.g.chain) {
         if (a.sh.cross_wave)
             fwd_kernel<P, D, NTC, true, true, false, false><<<grid, block, 0, st>>>(a);
         else

@@ -349,4 +349,24 @@ __device__ inline f32x4 ld16(const float* base, uint32_t byte_off) {
     return *reinterpret_cast<const f32x4*>(reinterpret_cast<const uint8_t*>(base) + byte_off);
 }
 
+// The c4v symmetry T_k of the L-by-L lattice applied to a site s = y L + x: the
+// kernels read a configuration as sigma o T_k, i.e. the spin at s is sigma(T_k(s)).
+// k: identity, rotations by 90, 180, 270 degrees, reflections x -> L-1-x,
+// y -> L-1-y, in the diagonal and in the anti-diagonal.
+__device__ inline int xform_site(int site, int k, int L) {
+    if (k == 0) return site;
+    const int y = site / L, x = site - y * L;
+    int xx = x, yy = y;
+    switch (k) {
+        case 1: xx = L - 1 - y; yy = x; break;
+        case 2: xx = L - 1 - x; yy = L - 1 - y; break;
+        case 3: xx = y; yy = L - 1 - x; break;
+        case 4: xx = L - 1 - x; break;
+        case 5: yy = L - 1 - y; break;
+        case 6: xx = y; yy = x; break;
+        default: xx = L - 1 - y; yy = L - 1 - x; break;
+    }
+    return yy * L + xx;
+}
+
 }  // namespace psr

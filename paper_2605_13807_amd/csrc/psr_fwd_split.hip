@@ -160,7 +160,9 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
     auto valid = [&](int c) -> bool { return (vmask >> c) & 1u; };
     auto tpos = [&](int c) -> int { return tk[c] & 0xFFFF; };
     auto kseq = [&](int c) -> int { return tk[c] >> 16; };
+    // spin at lattice site s of the configuration read as sigma o T_xform (c4v symmetry)
     auto spin = [&](int c, int site) -> int {
+        site = xform_site(site, a.xform, G.slx);
         const uint32_t* w = a.spins + (size_t)srow[c] * a.words_per_seq;
         const int v = (int)((w[site >> 5] >> (site & 31)) & 1u);
         const int fa = flip[c] & 0xFFFF, fb = (int)((uint32_t)flip[c] >> 16);
@@ -436,7 +438,7 @@ static int launch_split_t(const FwdArgs& a, hipStream_t st) {
 // d >= 128 (d = 64 keeps the lane-owns-all-units kernel of psr_fwd.hip, whose operand
 // sets fit in registers there; not measured with this kernel)
 bool split_kernel_applies(const Geom& g) {
-    return g.prec != kFP32 && !g.chain && g.d >= 128 && g.lx <= 16 * split_ntc(g.d);
+    return g.prec != kFP32 && !g.chain && g.patch == 1 && g.d >= 128 && g.lx <= 16 * split_ntc(g.d);
 }
 
 void split_shape(const Geom& g, FwdShape* s) {

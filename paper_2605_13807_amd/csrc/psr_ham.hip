@@ -310,6 +310,32 @@ __global__ void combine_kernel(const float* __restrict__ hi, const float* __rest
     if (b < B) out[b] = hi[b] + lo[b];
 }
 
+// log psi_c4v = 1/2 [logsumexp_k 2 log psi(sigma o T_k) - log 8] from the eight
+// (hi, lo) pairs, in FP64, kept as a (hi, lo) pair
+__global__ void c4v_combine_kernel(const float* __restrict__ hi8, const float* __restrict__ lo8, int64_t n,
+                                   float* __restrict__ out_hi, float* __restrict__ out_lo) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    double v[8];
+    double mx = -1e300;
+    for (int k = 0; k < 8; ++k) {
+        v[k] = 2.0 * ((double)hi8[k * n + q] + (double)lo8[k * n + q]);
+        mx = fmax(mx, v[k]);
+    }
+    double sum = 0.0;
+    for (int k = 0; k < 8; ++k) sum += exp(v[k] - mx);
+    const double r = 0.5 * (mx + log(sum) - log(8.0));
+    const float h = (float)r;
+    out_hi[q] = h;
+    if (out_lo) out_lo[q] = (float)(r - (double)h);
+}
+
+int launch_c4v_combine(const float* hi8, const float* lo8, int64_t n, float* out_hi, float* out_lo, hipStream_t st) {
+    if (n <= 0) return 0;
+    c4v_combine_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(hi8, lo8, n, out_hi, out_lo);
+    return (int)hipGetLastError();
+}
+
 int launch_combine_logpsi(const float* hi, const float* lo, int64_t B, float* out, hipStream_t st) {
     if (B == 0) return 0;
     combine_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(hi, lo, B, out);

@@ -35,8 +35,13 @@ __host__ __device__ inline int slot_unit(int s, int g) { return 16 * (s >> 2) + 
 // Model geometry as seen by the kernels.
 struct Geom {
     int chain;     // 1: Eq. (minGRU) chain, head on h; 0: 2D snake
-    int lx, ly, nl, d, prec;
+    int lx, ly;    // the grid the recurrence runs on: sites, or 2x2 patches (patch = 2)
+    int nl, d, prec;
+    int patch;     // 1: single-site inputs (K = 2); 2: 2x2 patches (K = 16)
+    int slx, sly;  // the spin lattice (lx, ly times patch)
+    int sym;       // 1: c4v-symmetrised log psi (eight transformed evaluations)
 };
+__host__ __device__ inline int n_states(const Geom& g) { return g.patch == 2 ? 16 : 2; }
 
 // Where one GEMM matrix of the model sits inside theta: element (r, k) is
 // theta[base + r * ld + coff + k] for r, k in [0, d).
@@ -93,6 +98,7 @@ struct FwdArgs {
     float* out_hi;            // [.] log psi, high part   (indexed by q)
     float* out_lo;            // [.] log psi, low part    (indexed by q) or NULL
     float* logp_site;         // [q][N] or NULL
+    int xform;                // 0..7: the spins are read as sigma o T_xform (c4v symmetry T_k)
 };
 
 // Launchers (return a hipError_t cast to int).
@@ -127,6 +133,8 @@ int launch_eloc_combine(int64_t B, const int64_t* offs, const float* diag, const
 int launch_stats(const double* x, int64_t B, double* stats, hipStream_t st);
 int launch_vmc_weights(const double* eloc, const double* stats, int64_t B, double* w, hipStream_t st);
 int launch_combine_logpsi(const float* hi, const float* lo, int64_t B, float* out, hipStream_t st);
+// c4v: (out_hi, out_lo)[q] = 1/2 [logsumexp_k 2 (hi + lo)[k n + q] - log 8], k = 0..7, in FP64
+int launch_c4v_combine(const float* hi8, const float* lo8, int64_t n, float* out_hi, float* out_lo, hipStream_t st);
 
 // Sampler (psr_sample.hip): workgroups of sequences, per-workgroup workspace
 int64_t sample_ws_per_wg_floats(const Geom& g);

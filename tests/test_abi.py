@@ -191,3 +191,26 @@ def test_logpsi_static_limits_on_host(P):
     assert code == -3
     assert b"static scratch" in L.psr_last_error()
     assert L.psr_logpsi_static(ctypes.byref(d), None, None, 0, None, None, None) == 0
+
+
+def test_patch_and_symmetry_checks_on_host(P):
+    """2x2 patches need even sides on the snake, c4v a square lattice; the backward and
+    the sampler reject both; log p per site is not defined under c4v.  Parameter
+    counts follow the oracle's layout."""
+    from oracle import model as OM
+    L = P.lib()
+    m = P.Model(P.SNAKE_2D, 5, 4, 2, 32, P.FP32, 0, 2, 0)
+    assert L.psr_param_count(ctypes.byref(m.c())) == -1
+    m = P.Model(P.SNAKE_2D, 6, 4, 2, 32, P.FP32, 0, 1, 1)
+    assert L.psr_param_count(ctypes.byref(m.c())) == -1
+    m = P.Model(P.SNAKE_2D, 6, 4, 2, 32, P.FP32, 0, 3, 0)
+    assert L.psr_param_count(ctypes.byref(m.c())) == -1
+    for lx, ly, nl, d in ((4, 4, 2, 32), (52, 52, 3, 256), (10, 6, 6, 64)):
+        m = P.Model(P.SNAKE_2D, lx, ly, nl, d, P.BF16, 0, 2, 0)
+        assert P.param_count(m) == OM.n_params(OM.Model("snake2d", lx, ly, nl, d, patch=2))
+    m = P.Model(P.SNAKE_2D, 4, 4, 2, 32, P.FP32, 0, 2, 1)
+    d = m.c()
+    p16 = ctypes.c_void_p(16)
+    assert L.psr_logpsi_backward(ctypes.byref(d), p16, p16, 1, p16, None, None, None, p16, 1 << 30, None) == -2
+    assert L.psr_sample(ctypes.byref(d), p16, p16, 1, p16, p16, p16, 1 << 30, None) == -2
+    assert L.psr_logpsi(ctypes.byref(d), p16, p16, 1, p16, p16, p16, 1 << 30, None) == -1
