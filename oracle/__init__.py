@@ -22,7 +22,11 @@ Modules
 ``symmetry``     the eight symmetries of the square lattice (c4v) and the
                  symmetrised log psi of the 2D runs.
 ``lru``          the 1D LRU ansatz (complex diagonal recurrence, GLU, residual):
-                 parameter layout and log psi by the sequential recurrence.
+                 parameter layout, log psi by the sequential recurrence, and
+                 exact site-by-site sampling.
+``lru_grad``     per-sample d log psi / d theta of the LRU by float64 torch
+                 autograd (a second, separately written complex forward) and
+                 central finite differences of ``lru``.
 ``grad``         per-sample d log psi / d theta by float64 torch autograd on
                  the CPU (a second, separately written forward), central finite
                  differences of ``model``, and the VMC batch statistics.

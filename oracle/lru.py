@@ -120,3 +120,27 @@ def site_logp(theta, spins, m: LruModel) -> np.ndarray:
 def logpsi(theta, spins, m: LruModel) -> np.ndarray:
     """log psi = (1/2) sum_t log p(sigma_t | sigma_<t), [B]."""
     return 0.5 * site_logp(theta, spins, m).sum(axis=1)
+
+
+def conditionals(theta, spins, m: LruModel) -> np.ndarray:
+    """p(sigma_t = 1 | sigma_<t) at every site, [B, N] (the two-way softmax of the head)."""
+    s = np.asarray(spins)
+    p_own = np.exp(site_logp(theta, s, m))
+    return np.where(s == 1, p_own, 1.0 - p_own)
+
+
+def sample(theta, uniforms, m: LruModel):
+    """Exact samples of the LRU chain and their log psi, drawn site by site (Sec. III.B).
+
+    sigma_t = 1 iff uniforms[b, t] < p(sigma_t = 1 | sigma_<t); the conditional at
+    site t is read from a forward over the spins drawn so far (one forward per site).
+    """
+    u = np.asarray(uniforms, dtype=np.float64)
+    B, N = u.shape
+    if N != m.n_sites:
+        raise ValueError("uniforms must be [B, n_sites]")
+    spins = np.zeros((B, N), dtype=np.int8)
+    for t in range(N):
+        p1 = conditionals(theta, spins, m)[:, t]
+        spins[:, t] = (u[:, t] < p1).astype(np.int8)
+    return spins, logpsi(theta, spins, m)

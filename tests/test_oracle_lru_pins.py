@@ -219,3 +219,85 @@ def test_planted_missing_input_shift_is_rejected(monkeypatch):
     with pytest.raises(AssertionError):
         test_normalised_over_all_configurations(2, 8, 4)
     monkeypatch.setattr(OL, "site_logp", orig_site_logp)
+
+
+# ----------------------------------------------------------------------------
+# The LRU's per-sample gradient (the separately written torch forward) and its
+# exact sampler: pinned by finite differences of the numpy oracle, by the score
+# identity over all configurations, and by the distribution of the draws.
+# ----------------------------------------------------------------------------
+
+from oracle import lru_grad as OLG  # noqa: E402
+
+
+@pytest.mark.parametrize("n,nl,d,dh", [(9, 2, 8, 6), (12, 3, 16, 16)])
+def test_lru_gradient_matches_finite_differences(n, nl, d, dh):
+    """O rows of the autograd forward equal central differences of lru.logpsi on a
+    random set of parameters (at least two per tensor), and its log psi equals the oracle's."""
+    m = OL.LruModel(n, nl, d, dh)
+    th = I.params(OL.n_params(m), d, 200 + n)
+    s = I.spins_bernoulli(3, n, 201 + n)
+    lp, O = OLG.per_sample_grad(th, s, m)
+    assert np.allclose(lp, OL.logpsi(th, s, m), atol=1e-12)
+    rng = I.rng(202)
+    idx, off = [], 0
+    for _, shp in OL.tensor_shapes(m):
+        k = int(np.prod(shp))
+        idx += list(rng.choice(np.arange(off, off + k), size=min(2, k), replace=False))
+        off += k
+    fd = np.stack([OLG.finite_difference(th, s, m, int(i)) for i in idx], axis=1)
+    assert np.abs(O[:, idx] - fd).max() <= 1e-7 * max(1.0, np.abs(fd).max())
+
+
+def test_lru_score_identity():
+    """sum_sigma p(sigma) d log psi / d theta = 0 over all 2^8 configurations (the
+    gradient of the normalisation; pins every component of the gradient at once)."""
+    m = OL.LruModel(8, 2, 6, 4)
+    th = 1.5 * I.params(OL.n_params(m), 6, 210)
+    cfg = np.array(list(itertools.product([0, 1], repeat=8)), dtype=np.int8)
+    lp, O = OLG.per_sample_grad(th, cfg, m)
+    p = np.exp(2.0 * lp)
+    assert abs(math.fsum(p) - 1.0) < 1e-12
+    assert np.abs(p @ O).max() < 1e-10
+
+
+def _chi2_p(samples, p):
+    """Pearson chi^2 p-value of integer-coded samples against probabilities p (bins with expectation >= 5)."""
+    from scipy.stats import chi2
+    n = samples.shape[1]
+    codes = samples.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
+    obs = np.bincount(codes, minlength=len(p)).astype(np.float64)
+    exp = p * samples.shape[0]
+    keep = exp >= 5
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    stat = ((o - e) ** 2 / e).sum()
+    return chi2.sf(stat, len(o) - 1)
+
+
+def test_lru_sampler_reproduces_brute_force_distribution():
+    """Exact site-by-site draws follow p(sigma) = prod_t p(sigma_t | sigma_<t) (Pearson chi^2 over
+    all 2^8 configurations); the same test rejects a planted mistake (the classes swapped)."""
+    m = OL.LruModel(8, 2, 8, 6)
+    th = 1.5 * I.params(OL.n_params(m), 8, 220)
+    cfg = np.array(list(itertools.product([0, 1], repeat=8)), dtype=np.int8)
+    p = np.exp(2.0 * OL.logpsi(th, cfg, m))
+    u = I.rng(221).random((20000, 8))
+    s, lp = OL.sample(th, u, m)
+    assert np.allclose(lp, OL.logpsi(th, s, m), atol=1e-12)
+    assert _chi2_p(s, p) > 1e-3
+    wrong = np.zeros_like(s)
+    for t in range(8):
+        wrong[:, t] = (u[:, t] < 1.0 - OL.conditionals(th, wrong, m)[:, t]).astype(np.int8)
+    assert _chi2_p(wrong, p) < 1e-6
+
+
+def test_lru_sampler_decision_rule():
+    m = OL.LruModel(6, 2, 8, 8)
+    th = I.params(OL.n_params(m), 8, 230)
+    s0, _ = OL.sample(th, np.zeros((2, 6)), m)
+    s1, _ = OL.sample(th, np.ones((2, 6)), m)
+    assert (s0 == 1).all() and (s1 == 0).all()
+    u = I.rng(231).random((10, 6))
+    s, _ = OL.sample(th, u, m)
+    assert ((u < OL.conditionals(th, s, m)) == (s == 1)).all()
