@@ -329,6 +329,42 @@ int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_ha
                          int64_t B, double* eloc, double* stats, float* logpsi, void* ws, size_t ws_bytes,
                          void* stream);
 
+/*
+ * Device workspace bytes of an LRU call for `batch` chains: op = PSR_OP_LOGPSI
+ * (psr_lru_logpsi, as psr_lru_workspace_bytes), PSR_OP_SAMPLE (psr_lru_sample)
+ * or PSR_OP_BACKWARD (psr_lru_backward with O = NULL; with O given, fewer
+ * bytes suffice).  Negative on error.
+ */
+int64_t psr_lru_op_workspace_bytes(const psr_lru_desc* m, int32_t op, int64_t batch);
+
+/*
+ * Exact autoregressive samples of chains under the LRU ansatz (Sec. III.B:
+ * p(sigma) = prod_t p(sigma_t | sigma_<t), sites left to right):
+ *     sigma_t = 1  iff  uniforms[b][t] < p(sigma_t = 1 | sigma_<t),
+ * p from the model's two-way head in FP32.  Equal uniforms give equal samples.
+ *   theta     device float[P];  uniforms  device float[B][n] in [0, 1)
+ *   spins     device int8[B][n]  (out);  logpsi  device float[B]  (out)
+ *   ws        device workspace of psr_lru_op_workspace_bytes(m, PSR_OP_SAMPLE, B) bytes
+ * Errors: PSR_EINVAL, PSR_ENOMEM (workspace too small), PSR_EDEVICE.  Queued on `stream`.
+ */
+int psr_lru_sample(const psr_lru_desc* m, const float* theta, const float* uniforms, int64_t B, int8_t* spins,
+                   float* logpsi, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Per-sample gradients O_s = d log psi(sigma_s) / d theta of the LRU ansatz
+ * (Sec. II.B Eq. (lru), Sec. II.G; the VMC gradient of Sec. III.B): the forward
+ * over each chain is recomputed and swept in reverse, the complex recurrence by
+ * the reverse scan Ghat_t = G_t + conj(lambda) Ghat_{t+1}.  FP32.
+ *   spins   device int8[B][n] in {0, 1}
+ *   O       device float[B][P] or NULL   (out) one gradient row per chain, parameter layout
+ *   logpsi  device float[B] or NULL      (out)
+ *   w, g    device double[B], double[P]  both NULL or both set: g = sum_s w_s O_s (FP64)
+ *   ws      device workspace of psr_lru_op_workspace_bytes(m, PSR_OP_BACKWARD, B) bytes
+ * At least one of O and g must be set.  Errors as psr_lru_sample.
+ */
+int psr_lru_backward(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B, float* O,
+                     float* logpsi, const double* w, double* g, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Timing of the forward (log psi) kernel, for measurement tools.  After

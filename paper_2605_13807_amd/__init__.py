@@ -19,7 +19,7 @@ import torch
 __all__ = [
     "Model", "Hamiltonian", "PsrError", "lib",
     "param_count", "param_offsets", "max_connected", "workspace_bytes",
-    "logpsi", "logpsi_static", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
+    "logpsi", "logpsi_static", "lru_sample", "lru_backward", "connected", "local_energy", "logpsi_backward", "vmc_weights", "check_spins",
     "LogPsi", "per_sample_grad", "timing_begin", "timing_end",
     "CHAIN_1D", "SNAKE_2D", "FP32", "BF16", "FP16", "SYM_NONE", "SYM_C4V", "TFIM", "HEISENBERG",
 ]
@@ -161,6 +161,12 @@ def lib() -> ctypes.CDLL:
         L.psr_lru_eloc_workspace_bytes.restype = i64
         L.psr_lru_local_energy.argtypes = [P(_LruDesc), vp, P(_HamDesc), vp, i64, vp, vp, vp, vp, sz, vp]
         L.psr_lru_local_energy.restype = ctypes.c_int
+        L.psr_lru_op_workspace_bytes.argtypes = [P(_LruDesc), i32, i64]
+        L.psr_lru_op_workspace_bytes.restype = i64
+        L.psr_lru_sample.argtypes = [P(_LruDesc), vp, vp, i64, vp, vp, vp, sz, vp]
+        L.psr_lru_sample.restype = ctypes.c_int
+        L.psr_lru_backward.argtypes = [P(_LruDesc), vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+        L.psr_lru_backward.restype = ctypes.c_int
         L.psr_check_spins.argtypes = [vp, i64, vp, vp]
         L.psr_check_spins.restype = ctypes.c_int
         L.psr_timing_begin.argtypes = []
@@ -298,6 +304,49 @@ def lru_local_energy(m: LruModel, theta: torch.Tensor, h: Hamiltonian, spins: to
     _check(lib().psr_lru_local_energy(ctypes.byref(m.c()), _ptr(theta), ctypes.byref(h.c()), _ptr(spins), B, _ptr(e),
                                       _ptr(st), _ptr(lp), _ptr(ws), ws.numel(), _stream(dev)))
     return e, st, lp
+
+
+def _lru_ws(m: LruModel, op: int, B: int, device) -> torch.Tensor:
+    n = lib().psr_lru_op_workspace_bytes(ctypes.byref(m.c()), op, B)
+    _check(int(n) if n < 0 else 0)
+    return torch.empty(max(1, int(n)), dtype=torch.uint8, device=device)
+
+
+def lru_sample(m: LruModel, theta: torch.Tensor, uniforms: torch.Tensor, ws: torch.Tensor | None = None):
+    """Exact autoregressive samples of LRU chains: (spins [B, n] int8, log psi [B] float32)."""
+    theta = _dev(theta, torch.float32, "theta")
+    u = _dev(uniforms, torch.float32, "uniforms")
+    B, N = u.shape
+    if N != m.n:
+        raise ValueError(f"uniforms has {N} sites, the model {m.n}")
+    spins = torch.empty(B, N, dtype=torch.int8, device=u.device)
+    lp = torch.empty(B, dtype=torch.float32, device=u.device)
+    if ws is None:
+        ws = _lru_ws(m, OP_SAMPLE, B, u.device)
+    _check(lib().psr_lru_sample(ctypes.byref(m.c()), _ptr(theta), _ptr(u), B, _ptr(spins), _ptr(lp), _ptr(ws),
+                                ws.numel(), _stream(u.device)))
+    return spins, lp
+
+
+def lru_backward(m: LruModel, theta: torch.Tensor, spins: torch.Tensor, w: torch.Tensor | None = None,
+                 want_O: bool = True, ws: torch.Tensor | None = None):
+    """(O [B, P] float32 or None, log psi [B], g [P] float64 or None) of LRU chains, g = sum_s w_s O_s."""
+    theta = _dev(theta, torch.float32, "theta")
+    spins = _dev(spins, torch.int8, "spins")
+    B = spins.shape[0]
+    dev = spins.device
+    P = lru_param_count(m)
+    O = torch.empty(B, P, dtype=torch.float32, device=dev) if want_O else None
+    lp = torch.empty(B, dtype=torch.float32, device=dev)
+    g = None
+    if w is not None:
+        w = _dev(w, torch.float64, "w")
+        g = torch.empty(P, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _lru_ws(m, OP_BACKWARD, B, dev)
+    _check(lib().psr_lru_backward(ctypes.byref(m.c()), _ptr(theta), _ptr(spins), B, _ptr(O), _ptr(lp), _ptr(w),
+                                  _ptr(g), _ptr(ws), ws.numel(), _stream(dev)))
+    return O, lp, g
 
 
 def connected(h: Hamiltonian, spins: torch.Tensor, max_conn: int | None = None, configs: bool = False):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpsr.so")
 SOURCES = ["psr_api.hip", "psr_fwd.hip", "psr_fwd_split.hip", "psr_ham.hip", "psr_bwd.hip", "psr_sample.hip",
-           "psr_lru.hip"]
+           "psr_lru.hip", "psr_lru_bwd.hip"]
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in device code (the host pass of
 # hipcc warns that it does not know the feature; that is harmless).
@@ -54,7 +54,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libpsr.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -843,6 +843,75 @@ int psr_lru_local_energy(const psr_lru_desc* m, const float* theta, const psr_ha
     return ok();
 }
 
+// LRU sampler / backward workspace: the prepared area, the per-chain workspace of
+// the chains in flight (backward), and the O rows when the caller wants only g
+static int64_t lru_aux_bytes(const LruGeom& g, int32_t op, int64_t B, bool need_O) {
+    int64_t b = align256(lru_prep_floats(g) * 4);
+    if (op == PSR_OP_BACKWARD) {
+        b += align256(lru_bwd_grid(g, B > 0 ? B : 1) * lru_bwd_chain_floats(g) * 4);
+        if (need_O) b += align256(B * lru_param_count(g) * 4);
+    }
+    return b;
+}
+
+int64_t psr_lru_op_workspace_bytes(const psr_lru_desc* m, int32_t op, int64_t batch) {
+    LruGeom g;
+    const int r = check_lru(m, &g);
+    if (r) return r;
+    if (batch < 0) return fail(PSR_EINVAL, "negative batch");
+    ok();
+    if (op == PSR_OP_LOGPSI) return lru_workspace_floats(g, batch) * (int64_t)sizeof(float);
+    if (op == PSR_OP_SAMPLE) return lru_aux_bytes(g, op, batch, false);
+    if (op == PSR_OP_BACKWARD) return lru_aux_bytes(g, op, batch, true);
+    return fail(PSR_EINVAL, "op %d is not PSR_OP_LOGPSI, PSR_OP_SAMPLE or PSR_OP_BACKWARD", op);
+}
+
+int psr_lru_sample(const psr_lru_desc* m, const float* theta, const float* uniforms, int64_t B, int8_t* spins,
+                   float* logpsi, void* ws, size_t ws_bytes, void* stream) {
+    LruGeom g;
+    int r = check_lru(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !uniforms || !spins || !logpsi) return fail(PSR_EINVAL, "theta, uniforms, spins and logpsi must not be NULL");
+    const int64_t need = lru_aux_bytes(g, PSR_OP_SAMPLE, B, false);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    hipStream_t st = as_stream(stream);
+    float* pw = static_cast<float*>(ws);
+    if ((r = dev_check(launch_lru_prep(g, theta, pw, st), "LRU prepare"))) return r;
+    if ((r = dev_check(launch_lru_sample(g, theta, pw, uniforms, B, spins, logpsi, st), "LRU sample"))) return r;
+    return ok();
+}
+
+int psr_lru_backward(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B, float* O,
+                     float* logpsi, const double* w, double* gout, void* ws, size_t ws_bytes, void* stream) {
+    LruGeom g;
+    int r = check_lru(m, &g);
+    if (r) return r;
+    if (B < 0) return fail(PSR_EINVAL, "negative batch");
+    if (B == 0) return ok();
+    if (!theta || !spins) return fail(PSR_EINVAL, "theta and spins must not be NULL");
+    if ((w == nullptr) != (gout == nullptr)) return fail(PSR_EINVAL, "w and g must be both set or both NULL");
+    if (!O && !gout) return fail(PSR_EINVAL, "nothing to compute: O and g are both NULL");
+    const int64_t need = lru_aux_bytes(g, PSR_OP_BACKWARD, B, O == nullptr);
+    if (!ws || (int64_t)ws_bytes < need)
+        return fail(PSR_ENOMEM, "workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
+    hipStream_t st = as_stream(stream);
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    float* pw = reinterpret_cast<float*>(base);
+    float* scratch = reinterpret_cast<float*>(base + align256(lru_prep_floats(g) * 4));
+    float* Ouse = O ? O
+                    : reinterpret_cast<float*>(base + align256(lru_prep_floats(g) * 4) +
+                                               align256(lru_bwd_grid(g, B) * lru_bwd_chain_floats(g) * 4));
+    if ((r = dev_check(launch_lru_prep(g, theta, pw, st), "LRU prepare"))) return r;
+    if ((r = dev_check(launch_lru_backward(g, theta, pw, spins, B, Ouse, logpsi, scratch, st), "LRU backward")))
+        return r;
+    if (gout && (r = dev_check(launch_weighted_sum(Ouse, B, lru_param_count(g), w, gout, st), "gradient sum")))
+        return r;
+    return ok();
+}
+
 int psr_check_spins(const int8_t* spins, int64_t n_values, int32_t* flag, void* stream) {
     if (n_values < 0) return fail(PSR_EINVAL, "negative size");
     if (n_values == 0) return ok();

@@ -166,6 +166,16 @@ int64_t lru_workspace_floats(const LruGeom& g, int64_t B);
 // logpsi_lo (or NULL): the low part of log psi (the FP64 sum as a float pair)
 int launch_lru_logpsi(const LruGeom& g, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
                       float* logpsi_lo, float* logp_site, float* scratch, hipStream_t st);
+// LRU sampler and backward (psr_lru_bwd.hip): a shared prepared area (transposed
+// matrices, lambda, e^gamma) and, for the backward, a workspace per chain in flight
+int64_t lru_prep_floats(const LruGeom& g);
+int64_t lru_bwd_chain_floats(const LruGeom& g);
+int64_t lru_bwd_grid(const LruGeom& g, int64_t B);
+int launch_lru_prep(const LruGeom& g, const float* theta, float* pw, hipStream_t st);
+int launch_lru_sample(const LruGeom& g, const float* theta, const float* pw, const float* u, int64_t B, int8_t* spins,
+                      float* logpsi, hipStream_t st);
+int launch_lru_backward(const LruGeom& g, const float* theta, const float* pw, const int8_t* spins, int64_t B,
+                        float* O, float* logpsi, float* scratch, hipStream_t st);
 // E_loc from per-sample connected slots (s * max_conn + k) and the two log psi (hi, lo) arrays
 int launch_lru_eloc_combine(int64_t B, int64_t max_conn, const int32_t* n_conn, const float* diag, const float* mel,
                             const float* lpc, const float* lpc_lo, const float* lps, const float* lps_lo, double* eloc,

@@ -151,3 +151,94 @@ def test_lru_local_energy_parity(P, kind, n, nl, d, dh, B):
     assert abs(st[0] - e.mean()) <= 1e-12 * max(1.0, abs(e.mean()))
     assert abs(st[1] - e.var()) <= 1e-10 * max(1.0, e.var())
     assert torch.equal(lp, P.lru_logpsi(m, th_d, torch.from_numpy(s).cuda()))
+
+
+# ----------------------------------------------------------------------------
+# The LRU's exact sampler and per-sample gradients (Sec. III.B), against the
+# float64 oracle (oracle/lru.py sampler, oracle/lru_grad.py autograd).
+# ----------------------------------------------------------------------------
+
+from oracle import lru_grad as OLG  # noqa: E402
+
+LRU_SAMPLE_CASES = [
+    # n, nl, d, dh, B
+    (12, 2, 16, 16, 64),
+    (9, 1, 32, 48, 20),       # d != d_h
+    (1, 2, 16, 16, 5),        # one site
+    (64, 3, 64, 64, 32),      # the Table I model
+    (256, 3, 64, 64, 8),
+]
+
+
+@pytest.mark.parametrize("n,nl,d,dh,B", LRU_SAMPLE_CASES)
+def test_lru_sampler_decisions(P, n, nl, d, dh, B):
+    """Every decision of the GPU sampler against the oracle's conditional on the GPU's own
+    prefix (float32 against float64: a disagreement is accepted only where u is within 2e-5
+    of p), log psi of the samples to the FP32 bar, and agreement with psr_lru_logpsi."""
+    print(f"LRU sampler n={n} nl={nl} d={d} dh={dh} B={B}", flush=True)
+    m, om, th, _ = _case(P, n, nl, d, dh, B, seed=7 * n + dh)
+    u = I.uniforms(B, n, 300 + n)
+    th_d = torch.from_numpy(th).cuda()
+    s, lp = P.lru_sample(m, th_d, torch.from_numpy(u).cuda())
+    s = s.cpu().numpy()
+    p1 = OL.conditionals(th, s, om)
+    bad = ((u < p1) != (s == 1)) & (np.abs(u - p1) > 2e-5)
+    assert not bad.any(), int(bad.sum())
+    ref = OL.logpsi(th, s, om)
+    got = lp.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 + 1e-6 * np.abs(ref).max()
+    again = P.lru_logpsi(m, th_d, torch.from_numpy(s).cuda()).cpu().numpy()
+    assert np.abs(again - got).max() <= 1e-5 + 1e-6 * np.abs(ref).max()
+
+
+def test_lru_sampler_distribution(P):
+    """Pearson chi^2 of 40000 GPU draws against the brute-force distribution of an 8-site chain."""
+    from scipy.stats import chi2
+    import itertools
+    m, om, th, _ = _case(P, 8, 2, 16, 16, 1, seed=88)
+    th = (1.5 * th).astype(np.float32)
+    cfg = np.array(list(itertools.product([0, 1], repeat=8)), dtype=np.int8)
+    p = np.exp(2.0 * OL.logpsi(th, cfg, om))
+    u = I.uniforms(40000, 8, 89)
+    s, _ = P.lru_sample(m, torch.from_numpy(th).cuda(), torch.from_numpy(u).cuda())
+    codes = s.cpu().numpy().astype(np.int64) @ (1 << np.arange(7, -1, -1))
+    obs = np.bincount(codes, minlength=256).astype(np.float64)
+    exp = p * 40000
+    keep = exp >= 5
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    pv = chi2.sf(((o - e) ** 2 / e).sum(), len(o) - 1)
+    print(f"  chi^2 p-value {pv:.3f}")
+    assert pv > 1e-3
+
+
+LRU_GRAD_CASES = [
+    # n, nl, d, dh, B
+    (10, 2, 16, 16, 6),
+    (9, 1, 32, 48, 5),        # d != d_h
+    (1, 2, 16, 16, 3),        # one site
+    (64, 3, 64, 64, 4),       # the Table I model
+    (256, 3, 64, 64, 2),
+]
+
+
+@pytest.mark.parametrize("n,nl,d,dh,B", LRU_GRAD_CASES)
+def test_lru_per_sample_gradient(P, n, nl, d, dh, B):
+    """O rows against float64 autograd (per sample ||dO|| / ||O|| <= 1e-4), log psi to the
+    FP32 bar, and the FP64 estimator equal to the weighted sum of exactly the returned rows."""
+    print(f"LRU gradient n={n} nl={nl} d={d} dh={dh} B={B}", flush=True)
+    m, om, th, s = _case(P, n, nl, d, dh, B, seed=11 * n + d)
+    lp_ref, O_ref = OLG.per_sample_grad(th, s, om)
+    th_d, s_d = torch.from_numpy(th).cuda(), torch.from_numpy(s).cuda()
+    w = torch.from_numpy(np.linspace(-1.0, 1.0, B)).cuda()
+    O, lp, g = P.lru_backward(m, th_d, s_d, w=w)
+    O64 = O.double().cpu().numpy()
+    rel = np.linalg.norm(O64 - O_ref, axis=1) / np.linalg.norm(O_ref, axis=1)
+    print(f"  per-sample rel grad err {rel.max():.3e}")
+    assert rel.max() <= 1e-4
+    assert np.abs(lp.cpu().numpy() - lp_ref).max() <= 1e-5 + 1e-6 * np.abs(lp_ref).max()
+    g_ref = w.cpu().numpy() @ O64
+    assert np.abs(g.cpu().numpy() - g_ref).max() <= 1e-9 * max(1.0, np.abs(g_ref).max())
+    # g alone (no O rows requested)
+    _, _, g2 = P.lru_backward(m, th_d, s_d, w=w, want_O=False)
+    assert torch.equal(g, g2)
