@@ -15,8 +15,8 @@ import math
 
 import torch
 
-from . import (OP_BACKWARD, OP_LOCAL_ENERGY, OP_SAMPLE, Hamiltonian, Model, _workspace, local_energy,
-               logpsi_backward, sample, vmc_weights)
+from . import (OP_BACKWARD, OP_LOCAL_ENERGY, OP_SAMPLE, Hamiltonian, LruModel, Model, _lru_ws, _workspace,
+               local_energy, logpsi_backward, lru_backward, lru_local_energy, lru_sample, sample, vmc_weights)
 
 
 class Adam:
@@ -52,6 +52,8 @@ def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, l
         log_every: int = 0):
     """Run `steps` VMC steps in place on `theta` (float32, device).  Returns [(mean E, variance)] per step.
 
+    ``m`` is a 2D snake / chain minGRU ``Model`` or a 1D ``LruModel`` (Table I's ansatz).
+
     ``lr`` is a constant or a function of the step index t = 0, 1, ... (e.g.
     ``lr_decay(eta0, delta0)``).  The uniforms of the sampler come from a seeded
     torch generator on the device, so a run is reproducible for a given seed.
@@ -68,16 +70,29 @@ def vmc(m: Model, h: Hamiltonian, theta: torch.Tensor, steps: int, batch: int, l
     gen.manual_seed(seed)
     sched = lr if callable(lr) else (lambda t: lr)
     opt = Adam(theta.numel(), dev, lr=sched(0))
-    ws_s = _workspace(m, OP_SAMPLE, batch, dev)
-    ws_e = _workspace(m, OP_LOCAL_ENERGY, batch, dev)
-    ws_b = _workspace(m, OP_BACKWARD, batch, dev)
+    lru = isinstance(m, LruModel)
+    if lru:
+        # the 1D LRU ansatz of Table I (psr_lru_* calls)
+        ws_s = _lru_ws(m, OP_SAMPLE, batch, dev)
+        ws_b = _lru_ws(m, OP_BACKWARD, batch, dev)
+        ws_e = None
+    else:
+        ws_s = _workspace(m, OP_SAMPLE, batch, dev)
+        ws_e = _workspace(m, OP_LOCAL_ENERGY, batch, dev)
+        ws_b = _workspace(m, OP_BACKWARD, batch, dev)
     hist = []
     for k in range(steps):
         u = torch.rand(batch, m.n_sites, generator=gen, device=dev, dtype=torch.float32)
-        spins, _ = sample(m, theta, u, ws=ws_s)
-        e, st, _ = local_energy(m, theta, h, spins, ws=ws_e)
-        w = vmc_weights(e, st)
-        _, _, g = logpsi_backward(m, theta, spins, w=w, want_O=False, ws=ws_b)
+        if lru:
+            spins, _ = lru_sample(m, theta, u, ws=ws_s)
+            e, st, _ = lru_local_energy(m, theta, h, spins)
+            w = vmc_weights(e, st)
+            _, _, g = lru_backward(m, theta, spins, w=w, want_O=False, ws=ws_b)
+        else:
+            spins, _ = sample(m, theta, u, ws=ws_s)
+            e, st, _ = local_energy(m, theta, h, spins, ws=ws_e)
+            w = vmc_weights(e, st)
+            _, _, g = logpsi_backward(m, theta, spins, w=w, want_O=False, ws=ws_b)
         opt.lr = sched(k)
         opt.step(theta, g)
         mean, var = (float(x) for x in st.cpu())

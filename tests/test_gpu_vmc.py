@@ -84,3 +84,31 @@ def test_vmc_table_one_small_chains(P):
         print(f"  {n:3d}  {e:.7f}  {exact:.7f}  {rel:.2e}  {ms:.2f}", flush=True)
         assert rel <= 1e-3
         assert e >= exact - 5e-4 * abs(exact)
+
+
+def test_vmc_lru_table_one_small_chains(P):
+    """Table I's own ansatz, the 1D LRU (3 layers, d = d_h = 64, GLU residual), trained on
+    the small open TFIM chains at h = 1 with the library's LRU sampler, E_loc and backward;
+    energy per site against the exact formula of Table I's caption.  Prints e(N), the
+    exact value, the relative error and the time per training step."""
+    import time
+
+    from paper_2605_13807_amd.vmc import lr_decay, vmc
+
+    print("\n  LRU (3 layers, d = d_h = 64), 1024 samples, 1500 steps", flush=True)
+    print("   N   e_vmc(N)      e_exact(N)    rel err    ms/step", flush=True)
+    for n in (6, 10, 16):
+        exact = OH.tfim_obc_exact_energy_per_site(n)
+        m = P.LruModel(n, 3, 64, 64)
+        th = torch.from_numpy(I.params(P.lru_param_count(m), 64, 900 + n)).cuda()
+        h = P.Hamiltonian(P.TFIM, n, 1, J=1.0, h=1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = vmc(m, h, th, steps=1500, batch=1024, lr=lr_decay(3e-3, 500.0), seed=7)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / 1500
+        e = float(np.mean([x[0] for x in hist[-100:]])) / n
+        rel = abs(e - exact) / abs(exact)
+        print(f"  {n:3d}  {e:.7f}  {exact:.7f}  {rel:.2e}  {ms:.2f}", flush=True)
+        assert rel <= 1e-3
+        assert e >= exact - 5e-4 * abs(exact)
