@@ -406,6 +406,20 @@ def main() -> int:
         lru["eloc_ms_per_call"] = round(ms_e, 3)
         lru["eloc_site_evals_per_s"] = (nsL * (nL + 1)) * nL / (ms_e / 1000.0)
         log(f"# lru E_loc: {ms_e:.2f} ms per {nsL} samples")
+        # a whole VMC training step of Table I's model at N = 256 (exact sampling, E_loc,
+        # per-sample backward, FP64 estimator, Adam), the quantity Table I reports per step
+        from paper_2605_13807_amd.vmc import vmc
+        thV = thL.clone()
+        vmc(mL, HL, thV, steps=1, batch=nsL, lr=1e-3, seed=11)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vmc(mL, HL, thV, steps=3, batch=nsL, lr=1e-3, seed=12)
+        torch.cuda.synchronize()
+        ms_v = 1000.0 * (time.perf_counter() - t0) / 3
+        lru["vmc_step_ms"] = round(ms_v, 2)
+        lru["vmc_step_note"] = ("one training step at N = 256, 1024 samples: sampler, E_loc, backward, estimator, "
+                                "Adam (Table I: 900 ms per step on an H100, context)")
+        log(f"# lru VMC step: {ms_v:.1f} ms")
 
     # CPU baseline: the float64 oracle on a bounded sample of the workload (the first
     # sample and as many of its connected configurations as fit in about 15 s, then

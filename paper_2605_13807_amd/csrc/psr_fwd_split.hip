@@ -10,7 +10,8 @@
 //   GEMM1  z_pre = W_z u + b_z, htilde = W_h [u, h_V] + b_h and D u for the
 //          wave's units, every column tile: the wave's weight fragments
 //          (read once per workgroup and row instead of once per wave) times
-//          the activations, u from LDS and h_V from the global row frontier.
+//          the activations, u from LDS and h_V staged into LDS from the global
+//          row frontier at the start of the layer (one load burst).
 //          Layer 0's u-part comes from 9-entry gather tables (u^(0) is two
 //          one-hot spins or zeros).
 //   scan   gates a = z (0 at a row start), b = (1 - z) htilde and the affine
@@ -25,7 +26,7 @@
 //          written to LDS as the next layer's u; after the last layer each
 //          wave's partial logit difference W_o[0] - W_o[1] is summed over the
 //          waves through LDS and the first wave forms log p.
-// Two barriers per layer and row, one more for the head.
+// Four barriers per layer and row (two on the first row), one more for the head.
 #include "psr_fwd_common.h"
 
 namespace psr {
@@ -96,7 +97,8 @@ __device__ inline f32x4 unpack4(uint2 vh, uint2 vl) {
                  (float)h1[1] + (float)l1[1]};
 }
 
-template <int P, int D, int W, int NTC>
+// XF: the spins are read through a c4v symmetry of the lattice (a.xform).
+template <int P, int D, int W, int NTC, bool XF>
 __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
     static_assert(P != kFP32, "split kernel: 16-bit operand pairs only");
     static_assert(Split<P>::kLoScale == 1.0f, "split kernel: unscaled low parts");
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
     auto kseq = [&](int c) -> int { return tk[c] >> 16; };
     // spin at lattice site s of the configuration read as sigma o T_xform (c4v symmetry)
     auto spin = [&](int c, int site) -> int {
-        site = xform_site(site, a.xform, G.slx);
+        if constexpr (XF) site = xform_site(site, a.xform, G.slx);
         const uint32_t* w = a.spins + (size_t)srow[c] * a.words_per_seq;
         const int v = (int)((w[site >> 5] >> (site & 31)) & 1u);
         const int fa = flip[c] & 0xFFFF, fb = (int)((uint32_t)flip[c] >> 16);
@@ -202,6 +204,23 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
             const uint8_t* fd = a.frag + a.pl.frag[l][3];
             const uint8_t* fc = a.frag + a.pl.frag[l][4];
             const uint32_t lo_l = (uint32_t)l * lbytes;   // this layer's frontier columns
+
+            // h_V of the whole row (the previous row's h^(l)) staged into the h buffer, which is
+            // free until this layer's scan: one load burst per layer instead of a dependent
+            // global load per column and K block in the h_V product
+            if (vert) {
+                constexpr int PIECES = 4 * D / 16;   // 16-byte pieces of a column
+                for (int e = threadIdx.x; e < seqs * lx * PIECES; e += W * 64) {
+                    const int col = e / PIECES, piece = e - col * PIECES;
+                    const int k = col / lx, t = col - k * lx;
+                    if (q0 + k >= q_end) continue;   // columns past the launch keep stale, finite values
+                    const int i = (j & 1) ? (lx - 1 - t) : t;
+                    const uint32_t src = (uint32_t)(k * nl + l) * lbytes + (uint32_t)(i * 4 * D + piece * 16);
+                    const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(fr, src, 0, 0));
+                    *reinterpret_cast<u32x4*>(lh + ((col % NTC) * 16 + col / NTC) * PITCH + piece * 16) = v;
+                }
+                __syncthreads();
+            }
 
             // ---- GEMM1: seeds, then the products on u (layers >= 1) and on h_V (rows >= 1)
             f32x4 az[UT][NTC], ah[UT][NTC], ad[UT][NTC];
@@ -276,10 +295,7 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
                             for (int tt = 0; tt < UT; ++tt) ad[tt][c] = mma3<P>(wd[tt], b, ad[tt][c]);
                         }
                         if (vert) {
-                            const uint32_t o = fro[c] + lo_l + kb * 32;
-                            const u32x4 hi = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(fr, o, 0, 0));
-                            const u32x4 lo = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(fr, o + 16, 0, 0));
-                            const u32x8 b = __builtin_shufflevector(hi, lo, 0, 1, 2, 3, 4, 5, 6, 7);
+                            const u32x8 b = ld32(lh + (c * 16 + r16) * PITCH + g * D + kb * 32);   // staged h_V
 #pragma unroll
                             for (int tt = 0; tt < UT; ++tt) ah[tt][c] = mma3<P>(wv[tt], b, ah[tt][c]);
                         }
@@ -303,6 +319,7 @@ __global__ void __launch_bounds__(W * 64) fwd_split_kernel(const FwdArgs a) {
                 }
             }
 
+            if (vert) __syncthreads();   // every wave is done with the staged h_V before h overwrites it
             // ---- gates and the chunked scan along the row; h to LDS
 #pragma unroll
             for (int tt = 0; tt < UT; ++tt) {
@@ -431,7 +448,10 @@ static int launch_split_t(const FwdArgs& a, hipStream_t st) {
     if (a.sh.waves != W || a.sh.ntc != NTC) return (int)hipErrorInvalidValue;   // shape from another model
     const int64_t blocks = (a.q_count + a.sh.seqs - 1) / a.sh.seqs;
     if (blocks <= 0) return 0;
-    fwd_split_kernel<P, D, W, NTC><<<dim3((unsigned)blocks), dim3(W * 64), 0, st>>>(a);
+    if (a.g.sym)
+        fwd_split_kernel<P, D, W, NTC, true><<<dim3((unsigned)blocks), dim3(W * 64), 0, st>>>(a);
+    else
+        fwd_split_kernel<P, D, W, NTC, false><<<dim3((unsigned)blocks), dim3(W * 64), 0, st>>>(a);
     return (int)hipGetLastError();
 }
 
