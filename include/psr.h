@@ -365,6 +365,18 @@ int psr_lru_sample(const psr_lru_desc* m, const float* theta, const float* unifo
 int psr_lru_backward(const psr_lru_desc* m, const float* theta, const int8_t* spins, int64_t B, float* O,
                      float* logpsi, const double* w, double* g, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- layout query ------------------------------------------------------- */
+
+/*
+ * Launch layout of the forward kernel for a model (for tools and tests that
+ * check the kernels' addressing on the host).  shape[0..8] = columns per
+ * workgroup, sequences per workgroup, 16-column tiles per wave, waves per
+ * workgroup, 1 if a sequence row may straddle waves, 1 if the row frontier is
+ * kept in LDS, 1 for the units-split kernel, sequences per forward launch of
+ * psr_logpsi for `batch` samples, and frontier bytes per sequence.
+ */
+int psr_forward_shape(const psr_model_desc* m, int64_t batch, int64_t* shape);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Timing of the forward (log psi) kernel, for measurement tools.  After

@@ -135,6 +135,8 @@ def lib() -> ctypes.CDLL:
         L.psr_workspace_bytes.restype = i64
         L.psr_logpsi.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp, sz, vp]
         L.psr_logpsi.restype = ctypes.c_int
+        L.psr_forward_shape.argtypes = [P(_ModelDesc), i64, P(i64)]
+        L.psr_forward_shape.restype = ctypes.c_int
         L.psr_logpsi_static.argtypes = [P(_ModelDesc), vp, vp, i64, vp, vp, vp]
         L.psr_logpsi_static.restype = ctypes.c_int
         L.psr_static_scratch_bytes.argtypes = []
@@ -211,6 +213,15 @@ def param_offsets(m: Model) -> list[int]:
     n = ctypes.c_int32(0)
     _check(lib().psr_param_offsets(ctypes.byref(m.c()), off, ctypes.byref(n)))
     return [int(off[k]) for k in range(n.value + 1)]
+
+
+def forward_shape(m: Model, batch: int) -> dict:
+    """The forward kernel's launch layout for `batch` samples (psr_forward_shape)."""
+    out = (ctypes.c_int64 * 9)()
+    _check(lib().psr_forward_shape(ctypes.byref(m.c()), batch, out))
+    keys = ("cols", "seqs", "ntc", "waves", "cross_wave", "lds_frontier", "split_kernel", "launch_seqs",
+            "frontier_seq_bytes")
+    return {k: int(out[i]) for i, k in enumerate(keys)}
 
 
 def max_connected(h: Hamiltonian) -> int:

@@ -510,6 +510,25 @@ int psr_logpsi(const psr_model_desc* m, const float* theta, const int8_t* spins,
     return ok();
 }
 
+int psr_forward_shape(const psr_model_desc* m, int64_t batch, int64_t* shape) {
+    Geom g;
+    const int r = check_model(m, &g);
+    if (r) return r;
+    if (!shape) return fail(PSR_EINVAL, "shape must not be NULL");
+    if (batch < 0) return fail(PSR_EINVAL, "negative batch");
+    const FwdShape sh = fwd_shape(g);
+    shape[0] = sh.cols;
+    shape[1] = sh.seqs;
+    shape[2] = sh.ntc;
+    shape[3] = sh.waves;
+    shape[4] = sh.cross_wave;
+    shape[5] = sh.lds_frontier;
+    shape[6] = sh.split_kernel;
+    shape[7] = batch > 0 ? logpsi_chunk(g, batch) : 0;
+    shape[8] = frontier_seq_bytes(g);
+    return ok();
+}
+
 int64_t psr_static_scratch_bytes(void) { return (int64_t)kStaticScratchBytes; }
 
 int psr_logpsi_static(const psr_model_desc* m, const float* theta, const int8_t* spins, int64_t B, float* logpsi,
